@@ -1,0 +1,215 @@
+/*
+ * stglbm.h -- C ABI of the STG-LBM hot path on one MI355X (gfx950).
+ *
+ * The library advances a regularized D3Q19 lattice-Boltzmann large-eddy
+ * simulation (Smagorinsky eddy viscosity) of a 3-D channel whose inlet plane
+ * is fed by a synthetic turbulence generator (STG) built from RANS data, and
+ * whose outlet is a regularized pressure boundary with a sponge zone before
+ * it.  Method: Xue, Yao & Davidson, "Synthetic turbulence generator for
+ * lattice Boltzmann method at the interface between RANS and LES"
+ * (Methodology section; STG section; Algorithm 1; Numerical setup section).
+ *
+ * Geometry.  Lattice NX x NY x NZ.  x is streamwise: inlet plane x = 0,
+ * outlet plane x = NX-1 (or periodic).  y is wall-normal with halfway
+ * bounce-back walls at y = -1/2 and y = NY-1/2.  z is spanwise and periodic.
+ *
+ * Memory.  The caller owns all device memory: init_lattice carves one
+ * caller-provided workspace of stglbm_footprint() bytes and the library
+ * never allocates device memory.  The caller also owns the HIP stream
+ * (hipStream_t passed as void*); every kernel of a handle runs on it.
+ * Host arrays passed in are only read during the call.
+ *
+ * Distributions.  Stored as deviations g_i = f_i - w_i in two buffers
+ * (read one, write the other, swapped every step), as FP32, FP16 or BF16
+ * (round to nearest even); arithmetic is FP32, statistics FP64.
+ * Layout [19][NZ][NY][NX], x fastest; population order: rest;
+ * +x, -x, +y, -y, +z, -z; (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0),
+ * (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1),
+ * (0,-1,1).
+ *
+ * Errors.  Every call returns an int: STGLBM_OK (0) or a negative code;
+ * stglbm_last_error() gives the message.  stglbm_step is asynchronous: an
+ * instability detected on the device (density deviation outside
+ * (-0.5, 0.5), NaN, or |u_bc,x| >= 0.3 c_s at an inlet node) is reported as
+ * STGLBM_E_UNSTABLE by the next synchronizing call (get_*, set_*,
+ * checkpoint, sync).  A handle is not thread-safe; distinct handles are
+ * independent and may run concurrently on different streams.
+ */
+#ifndef STGLBM_H
+#define STGLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stglbm_ctx* stglbm_t;
+
+enum stglbm_status {
+  STGLBM_OK = 0,
+  STGLBM_E_INVAL = -1,          /* bad argument, size or descriptor            */
+  STGLBM_E_NOMEM = -2,          /* workspace smaller than stglbm_footprint()   */
+  STGLBM_E_HIP = -3,            /* a HIP runtime call or kernel launch failed  */
+  STGLBM_E_STATE = -4,          /* call out of order (e.g. step before inlet)  */
+  STGLBM_E_UNSTABLE = -5,       /* device flagged an instability               */
+  STGLBM_E_REALIZABILITY = -6   /* Reynolds stress not positive semi-definite  */
+};
+
+enum stglbm_store { STGLBM_F32 = 0, STGLBM_F16 = 1, STGLBM_BF16 = 2 };
+
+/* Lattice description (all lattice units).  Field order and padding are
+ * part of the ABI. */
+typedef struct {
+  int32_t nx, ny, nz;       /* lattice size; nx, ny >= 2, nz >= 1, cells < 2^31      */
+  int32_t store;            /* enum stglbm_store                                     */
+  int32_t periodic_x;       /* 1: x periodic, no inlet/outlet/sponge                  */
+  int32_t sponge_cells;     /* L_s: sponge over x in [NX-1-L_s, NX-1]; 0 = off        */
+  int32_t max_modes;        /* capacity of the STG mode tables (0 if periodic_x)      */
+  int32_t max_rans;         /* capacity of the RANS input staging (0 if periodic_x)   */
+  double nu_lb;             /* molecular viscosity; tau0 = 1/2 + 3 nu (eq. lbe-nu)    */
+  double cs_smag;           /* Smagorinsky Cs; the paper's C = Cs^2 (eq. smogrinsky)  */
+  double force[3];          /* Guo volume acceleration (eq. bodyforce)               */
+  double rho_out;           /* outlet density                                         */
+  double sponge_K;          /* eq. sponge_visco: nu (1 + K s^p)                       */
+  double sponge_p;
+} stglbm_lattice_desc;
+
+/* RANS data at the interface and STG parameters (Algorithm 1, RANS section
+ * step 2 and LBM section steps 1-4).  Physical units (m, s). */
+typedef struct {
+  int32_t n_rans;           /* number of RANS points (FV cell centres)               */
+  int32_t n_modes;          /* N Fourier modes (eq. aux_vec), 1 <= N <= max_modes     */
+  const double* y;          /* [n_rans] strictly increasing, inside (0, 2 delta)     */
+  const double* U3;         /* [n_rans][3] mean velocity                             */
+  const double* k;          /* [n_rans] turbulent kinetic energy                     */
+  const double* omega;      /* [n_rans] specific dissipation rate                    */
+  const double* R6;         /* [n_rans][6] R11, R22, R33, R12, R13, R23              */
+  double delta;             /* channel half-height; the lattice spans 2 delta in y   */
+  double nu_phys;           /* kinematic viscosity (for the Kolmogorov scale)        */
+  double c_x;               /* length conversion (eq. c_factor): 2 delta / NY         */
+  double c_t;               /* time conversion (eq. c_factor)                        */
+  double U_b;               /* RANS bulk velocity used in the pseudo-position (eq. psu) */
+  double alpha;             /* k^n = k_min (1+alpha)^(n-1); <= 0: chosen so k^N = k_max */
+  uint64_t seed;            /* SplitMix64 seed of the mode draw                      */
+  double C_l;               /* l_e = min(2 d_w, C_l l_t), 3.0                        */
+  double C_mu;              /* l_t = sqrt(k)/(C_mu omega), 0.09                      */
+  int32_t strict;           /* 1: a negative Cholesky radicand is an error            */
+  int32_t reserved;
+} stglbm_rans_inlet;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int stglbm_version(void);
+
+/* Message of a status code. */
+const char* stglbm_status_string(int status);
+
+/* Unit conversion for a channel (Numerical setup section; eqs. c_factor,
+ * u_transfer, lbe-nu): c_x = 2 delta / NY, c_t = u_b_lb c_x / U_b,
+ * nu_lb = nu_phys c_t / c_x^2.  Host arithmetic in FP64. */
+int stglbm_derive_units(double delta, int32_t ny, double u_b_lb, double U_b, double nu_phys,
+                        double* c_x, double* c_t, double* nu_lb);
+
+/* Bytes of device workspace a lattice needs (256-byte aligned pieces). */
+int stglbm_footprint(const stglbm_lattice_desc* desc, uint64_t* bytes);
+
+/* Create a handle on a caller-owned workspace (>= footprint bytes, 256-byte
+ * aligned) and stream.  The state becomes rest, f_i = w_i (g = 0; Results
+ * section), the step counter 0, the statistics empty.  Launches work on the
+ * stream and returns without waiting. */
+int stglbm_init_lattice(const stglbm_lattice_desc* desc, void* d_workspace, uint64_t ws_bytes,
+                        void* hip_stream, stglbm_t* out);
+
+/* Install the RANS inlet and precompute the STG tables on the device in FP64
+ * (Algorithm 1, LBM steps 1-4): interpolation to the lattice rows, Cholesky
+ * factor (eq. cholesky), l_t, l_e, l_cut (eq. lcut), wavenumbers, the
+ * modified von Karman weights q^n (eq. qn), the SplitMix64 mode draw (eq. dn)
+ * and the spanwise phase table.  Synchronizes the stream.
+ * E_STATE if periodic_x; E_INVAL on bad sizes; E_REALIZABILITY if strict and
+ * a radicand was negative (otherwise it is clamped to 0 and counted). */
+int stglbm_set_rans_inlet(stglbm_t h, const stglbm_rans_inlet* in);
+
+/* Inlet velocity plane at step index t_step (the state being produced),
+ * eqs. aux_vec, psu, v_fluc, u_phys, u_transfer, in lattice units.
+ * Writes [NY][NZ][3] FP32 to d_u_plane (device) if non-null, else to the
+ * handle's own inlet buffer.  Asynchronous on the stream. */
+int stglbm_stg_generate(stglbm_t h, int64_t t_step, float* d_u_plane);
+
+/* Advance n_steps time steps (Algorithm 1, steps 5-12): for each step the STG
+ * plane at t+1, then one fused pass: pull streaming with bounce-back walls and
+ * spanwise wrap, regularized inlet rebuild (eqs. f_i .. bc_eq), regularized
+ * pressure outlet, moments, Smagorinsky tau_eff (eqs. strain, tau_eff), the
+ * sponge (eq. sponge_visco), regularized BGK collision with Guo force, and,
+ * while sampling, FP64 statistics.  Asynchronous on the stream. */
+int stglbm_step(stglbm_t h, int32_t n_steps);
+
+/* Zero the statistics and start sampling every subsequent step. */
+int stglbm_stats_reset(stglbm_t h);
+/* Stop sampling (statistics are kept). */
+int stglbm_stats_stop(stglbm_t h);
+
+/* Statistics sums [NX][NY][9] FP64 over z and sampled steps of
+ * u, v, w, uu, vv, ww, uv, uw, vw (velocity of each cell after streaming and
+ * any boundary rebuild, the one the collision used; eq. v_rms inputs), and
+ * the number of sampled steps.  Synchronizes. n = NX*NY*9. */
+int stglbm_get_stats(stglbm_t h, double* h_out, uint64_t n, int64_t* n_samples);
+
+/* Current distributions f = w + g as FP64 [19][NZ][NY][NX]; synchronizes.
+ * Uses the inactive buffer as staging. n = 19*NX*NY*NZ. */
+int stglbm_get_f(stglbm_t h, double* h_out, uint64_t n);
+/* f = w + g for the planes x0 <= x < x1 only, FP64 [19][NZ][NY][x1-x0];
+ * synchronizes. n = 19*NZ*NY*(x1-x0). */
+int stglbm_get_f_planes(stglbm_t h, int32_t x0, int32_t x1, double* h_out, uint64_t n);
+/* Device address and size in bytes of the current distributions g (store
+ * type, [19][NZ][NY][NX]); valid until the next step or restore. */
+int stglbm_state_view(stglbm_t h, void** d_g, uint64_t* bytes);
+/* Replace the distributions by f (rounded to the store type). Synchronizes. */
+int stglbm_set_f(stglbm_t h, const double* h_in, uint64_t n);
+
+/* Mode table [N][8]: k^n, d^n (3), sigma^n (3), phi^n (FP64). Synchronizes. */
+int stglbm_get_modes(stglbm_t h, double* h_out, uint64_t n);
+/* Per-row inlet table [NY][STGLBM_ROW_FIELDS] FP64. Synchronizes. */
+#define STGLBM_ROW_FIELDS 18   /* U(3) k omega R(6) a11 a21 a22 a31 a32 a33 l_e */
+int stglbm_get_inlet_rows(stglbm_t h, double* h_out, uint64_t n);
+/* Inlet scalars [8]: L_e, k_min, k_max, alpha, k_cut, clamps, U_b, n_modes. */
+int stglbm_get_inlet_scalars(stglbm_t h, double* h_out, uint64_t n);
+/* sqrt(q^n) per row [NY][N] FP64. Synchronizes. */
+int stglbm_get_sqrtq(stglbm_t h, double* h_out, uint64_t n);
+
+/* Completed steps. */
+int stglbm_get_step(stglbm_t h, int64_t* t);
+
+/* Switch the handle to another caller-owned stream. */
+int stglbm_set_stream(stglbm_t h, void* hip_stream);
+
+/* Wait for the stream and report a device-side instability. */
+int stglbm_sync(stglbm_t h);
+
+/* Checkpoint: step counter, sampling state, distributions and statistics.
+ * Restoring needs a handle with the same descriptor and the same inlet input
+ * (checked by a hash); a restored run continues bit for bit. */
+int stglbm_checkpoint_size(stglbm_t h, uint64_t* bytes);
+int stglbm_checkpoint(stglbm_t h, void* h_buf, uint64_t n);
+int stglbm_restore(stglbm_t h, const void* h_buf, uint64_t n);
+
+/* Timing of the fused step kernel and the STG kernel with HIP events on the
+ * handle's stream while enabled.  out[4] = {step-kernel ms total, launches,
+ * STG-kernel ms total, launches}; reading synchronizes and clears. */
+int stglbm_profile(stglbm_t h, int32_t enable);
+int stglbm_profile_read(stglbm_t h, double* out, uint64_t n);
+
+/* Plain device copy of `bytes` (multiple of 16) on a stream: the bandwidth
+ * calibration kernel for counter and roofline measurements. */
+int stglbm_copy_probe(const void* d_src, void* d_dst, uint64_t bytes, void* hip_stream);
+
+/* Free the host handle (the workspace stays the caller's). */
+int stglbm_destroy(stglbm_t h);
+
+/* Last error message of a handle (or of the library if h is NULL). */
+const char* stglbm_last_error(stglbm_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STGLBM_H */

@@ -1,0 +1,636 @@
+// C ABI of libstglbm (declared in include/stglbm.h).
+//
+// Host-side duties only: validate arguments, carve the caller's workspace,
+// choose the launch shape, sequence the kernels on the caller's stream, move
+// data for the test/ops helpers and report device flags.  Every step of the
+// method runs in the kernels of lattice_kernels.hip and inlet_kernels.hip.
+#include "stglbm.h"
+#include "stglbm_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace stglbm;
+
+namespace {
+
+constexpr int kVersion = 10000;        // 1.0.0
+constexpr uint64_t kAlign = 256;
+constexpr uint32_t kCkptMagic = 0x5354474cu;   // "STGL"
+constexpr uint32_t kCkptVersion = 1;
+
+thread_local std::string g_lib_error;
+
+struct Layout {
+  uint64_t g[2] = {0, 0}, stats = 0, sponge = 0, flag = 0, ubc = 0, rans = 0, rows = 0, modes = 0,
+           sqrtq = 0, bz = 0, sig = 0, scalars = 0, total = 0;
+  int nxt = 0, slots = 0, lw = 0, nblocks = 0;
+};
+
+uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int store_bytes(int store) { return store == STGLBM_F32 ? 4 : 2; }
+
+const char* check_desc(const stglbm_lattice_desc* d) {
+  if (!d) return "null descriptor";
+  if (d->nx < 2 || d->ny < 2 || d->nz < 1) return "lattice must have nx >= 2, ny >= 2, nz >= 1";
+  if (static_cast<long long>(d->nx) * d->ny * d->nz > 0x7fffffffLL) return "lattice has 2^31 cells or more";
+  if (d->store < 0 || d->store > 2) return "unknown store type";
+  if (!(d->nu_lb > 0.0) || !std::isfinite(d->nu_lb)) return "nu_lb must be positive";
+  if (!(d->cs_smag >= 0.0)) return "cs_smag must be >= 0";
+  if (!d->periodic_x) {
+    if (d->max_modes < 1 || d->max_rans < 2) return "an inlet channel needs max_modes >= 1 and max_rans >= 2";
+    if (!(d->rho_out > 0.0)) return "rho_out must be positive";
+    if (d->sponge_cells < 0 || d->sponge_cells >= d->nx - 1) return "sponge_cells out of range";
+  }
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(d->force[a])) return "force must be finite";
+  return nullptr;
+}
+
+Layout make_layout(const stglbm_lattice_desc* d) {
+  Layout L;
+  const uint64_t cells = static_cast<uint64_t>(d->nx) * d->ny * d->nz;
+  L.nxt = (d->nx + 63) / 64;
+  const int base = L.nxt * d->ny;
+  const int zmax = (d->nz + kWavesZ - 1) / kWavesZ;
+  int slots = (2048 + base - 1) / base;            // aim for >= 2048 blocks
+  if (slots < 1) slots = 1;
+  if (slots > zmax) slots = zmax;
+  int lw = (d->nz + kWavesZ * slots - 1) / (kWavesZ * slots);
+  if (const char* env = std::getenv("STGLBM_LW")) {
+    const int v = std::atoi(env);
+    if (v >= 1) lw = v;
+  }
+  L.lw = lw;
+  L.slots = (d->nz + kWavesZ * lw - 1) / (kWavesZ * lw);
+  L.nblocks = base * L.slots;
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const uint64_t gbytes = static_cast<uint64_t>(kQ) * cells * store_bytes(d->store);
+  L.g[0] = take(gbytes);
+  L.g[1] = take(gbytes);
+  L.stats = take(static_cast<uint64_t>(L.slots) * 9 * d->nx * d->ny * sizeof(double));
+  L.sponge = take(static_cast<uint64_t>(d->nx) * sizeof(float));
+  L.flag = take(2 * sizeof(int));
+  if (!d->periodic_x) {
+    L.ubc = take(static_cast<uint64_t>(d->ny) * d->nz * 3 * sizeof(float));
+    L.rans = take(static_cast<uint64_t>(d->max_rans) * 12 * sizeof(double));
+    L.rows = take(static_cast<uint64_t>(d->ny) * kRowFields * sizeof(double));
+    L.modes = take(static_cast<uint64_t>(d->max_modes) * kModeFields * sizeof(double));
+    L.sqrtq = take(static_cast<uint64_t>(d->ny) * d->max_modes * sizeof(double));
+    L.bz = take(static_cast<uint64_t>(d->max_modes) * d->nz * sizeof(float2));
+    L.sig = take(static_cast<uint64_t>(d->max_modes) * sizeof(float4));
+    L.scalars = take(kScalars * sizeof(double));
+  }
+  L.total = off;
+  return L;
+}
+
+uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+  const unsigned char* p = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= p[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+struct CkptHeader {
+  uint32_t magic, version;
+  int32_t nx, ny, nz, store, periodic_x, slots;
+  uint64_t inlet_hash;
+  int64_t t, n_samples;
+  int32_t sampling, n_modes;
+  uint64_t g_bytes, stats_bytes;
+};
+
+}  // namespace
+
+struct stglbm_ctx {
+  stglbm_lattice_desc d{};
+  Layout L;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  int cur = 0;
+  int64_t t = 0;
+  int64_t n_samples = 0;
+  bool sampling = false;
+  bool inlet_ready = false;
+  int n_modes = 0;
+  uint64_t inlet_hash = 0;
+  double c_x = 0, c_t = 0, U_b = 0, L_e = 0;
+  std::string err;
+  bool prof = false;
+  std::vector<hipEvent_t> ev_step, ev_stg;   // start/stop pairs
+  size_t n_step = 0, n_stg = 0;
+
+  template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
+  void* gbuf(int k) { return ws + L.g[k]; }
+  uint64_t cells() const { return static_cast<uint64_t>(d.nx) * d.ny * d.nz; }
+  uint64_t gbytes() const { return static_cast<uint64_t>(kQ) * cells() * store_bytes(d.store); }
+};
+
+namespace {
+
+int fail(stglbm_t h, int code, const std::string& msg) {
+  if (h) h->err = msg; else g_lib_error = msg;
+  return code;
+}
+
+int hip_fail(stglbm_t h, hipError_t e, const char* what) {
+  return fail(h, STGLBM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_CHECK(h, expr, what)                  \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(h, e_, what); \
+  } while (0)
+
+// Wait for the stream and turn device flags into an error.
+int sync_and_check(stglbm_t h) {
+  HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  int flag = 0;
+  HIP_CHECK(h, hipMemcpy(&flag, h->at<int>(h->L.flag), sizeof(int), hipMemcpyDeviceToHost), "hipMemcpy flag");
+  if (flag & kFlagDensity) return fail(h, STGLBM_E_UNSTABLE, "density deviation out of (-0.5, 0.5) or NaN in the lattice");
+  if (flag & kFlagInletMach) return fail(h, STGLBM_E_UNSTABLE, "inlet velocity |u_x| >= 0.3 c_s");
+  return STGLBM_OK;
+}
+
+hipEvent_t pooled_event(std::vector<hipEvent_t>& pool, size_t idx) {
+  while (pool.size() <= idx) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pool.push_back(e);
+  }
+  return pool[idx];
+}
+
+StepParams step_params(stglbm_t h) {
+  StepParams p{};
+  const stglbm_lattice_desc& d = h->d;
+  p.gin = h->gbuf(h->cur);
+  p.gout = h->gbuf(1 - h->cur);
+  p.plane = static_cast<long long>(h->cells());
+  p.nx = d.nx; p.ny = d.ny; p.nz = d.nz;
+  p.nxt = h->L.nxt; p.slots = h->L.slots; p.lw = h->L.lw; p.nblocks = h->L.nblocks;
+  p.remap = (p.nblocks % 8 == 0) ? 1 : 0;
+  p.periodic_x = d.periodic_x;
+  p.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
+  const double tau0 = 0.5 + 3.0 * d.nu_lb;
+  p.tau0 = static_cast<float>(tau0);
+  p.tau0_sq = static_cast<float>(tau0 * tau0);
+  p.s0 = static_cast<float>(3.0 * d.nu_lb);
+  p.c18 = static_cast<float>(18.0 * std::sqrt(2.0) * d.cs_smag * d.cs_smag);
+  p.fx = static_cast<float>(d.force[0]);
+  p.fy = static_cast<float>(d.force[1]);
+  p.fz = static_cast<float>(d.force[2]);
+  p.rho_out_m1 = static_cast<float>(d.rho_out - 1.0);
+  p.inv_rho_out = static_cast<float>(1.0 / d.rho_out);
+  p.sponge = h->at<float>(h->L.sponge);
+  p.ubc = d.periodic_x ? nullptr : h->at<float>(h->L.ubc);
+  p.stats = h->at<double>(h->L.stats);
+  p.flag = h->at<int>(h->L.flag);
+  return p;
+}
+
+int launch_plane(stglbm_t h, int64_t t_step, float* out) {
+  StgParams s{};
+  s.modes = h->at<double>(h->L.modes);
+  s.sqrtq = h->at<double>(h->L.sqrtq);
+  s.bz = h->at<float2>(h->L.bz);
+  s.sig = h->at<float4>(h->L.sig);
+  s.rows = h->at<double>(h->L.rows);
+  s.out = out ? out : h->at<float>(h->L.ubc);
+  s.flag = h->at<int>(h->L.flag);
+  s.ny = h->d.ny; s.nz = h->d.nz; s.n_modes = h->n_modes;
+  s.c_x = h->c_x;
+  s.conv = h->c_t / h->c_x;
+  const double kTwoPi = 6.283185307179586476925;
+  s.tphase = kTwoPi * (0.0 - h->U_b * (static_cast<double>(t_step) * h->c_t)) / h->L_e;
+  s.mach_limit = static_cast<float>(0.3 / std::sqrt(3.0));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof) {
+    e0 = pooled_event(h->ev_stg, 2 * h->n_stg);
+    e1 = pooled_event(h->ev_stg, 2 * h->n_stg + 1);
+    if (e0 && e1) HIP_CHECK(h, hipEventRecord(e0, h->stream), "hipEventRecord");
+  }
+  HIP_CHECK(h, launch_stg(s, h->stream), "STG plane kernel launch");
+  if (h->prof && e0 && e1) {
+    HIP_CHECK(h, hipEventRecord(e1, h->stream), "hipEventRecord");
+    ++h->n_stg;
+  }
+  return STGLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int stglbm_version(void) { return kVersion; }
+
+const char* stglbm_status_string(int s) {
+  switch (s) {
+    case STGLBM_OK: return "ok";
+    case STGLBM_E_INVAL: return "invalid argument";
+    case STGLBM_E_NOMEM: return "workspace too small";
+    case STGLBM_E_HIP: return "HIP error";
+    case STGLBM_E_STATE: return "call out of order";
+    case STGLBM_E_UNSTABLE: return "instability detected";
+    case STGLBM_E_REALIZABILITY: return "Reynolds stress not realizable";
+    default: return "unknown status";
+  }
+}
+
+int stglbm_derive_units(double delta, int32_t ny, double u_b_lb, double U_b, double nu_phys,
+                        double* c_x, double* c_t, double* nu_lb) {
+  if (!(delta > 0) || ny < 1 || !(u_b_lb > 0) || !(U_b > 0) || !(nu_phys > 0) || !c_x || !c_t || !nu_lb)
+    return fail(nullptr, STGLBM_E_INVAL, "derive_units: arguments must be positive");
+  *c_x = 2.0 * delta / ny;
+  *c_t = u_b_lb * (*c_x) / U_b;
+  *nu_lb = nu_phys * (*c_t) / ((*c_x) * (*c_x));
+  return STGLBM_OK;
+}
+
+int stglbm_footprint(const stglbm_lattice_desc* desc, uint64_t* bytes) {
+  if (const char* m = check_desc(desc)) return fail(nullptr, STGLBM_E_INVAL, m);
+  if (!bytes) return fail(nullptr, STGLBM_E_INVAL, "null output");
+  *bytes = make_layout(desc).total;
+  return STGLBM_OK;
+}
+
+int stglbm_init_lattice(const stglbm_lattice_desc* desc, void* d_workspace, uint64_t ws_bytes,
+                        void* hip_stream, stglbm_t* out) {
+  if (!out) return fail(nullptr, STGLBM_E_INVAL, "null handle output");
+  *out = nullptr;
+  if (const char* m = check_desc(desc)) return fail(nullptr, STGLBM_E_INVAL, m);
+  if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign))
+    return fail(nullptr, STGLBM_E_INVAL, "workspace must be non-null and 256-byte aligned");
+  Layout L = make_layout(desc);
+  if (ws_bytes < L.total) return fail(nullptr, STGLBM_E_NOMEM, "workspace smaller than stglbm_footprint()");
+  stglbm_t h = new (std::nothrow) stglbm_ctx();
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "host allocation failed");
+  h->d = *desc;
+  h->L = L;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->ws = static_cast<char*>(d_workspace);
+  // rest state g = 0, statistics 0, flags 0 (fill kernels: safe under graph capture)
+  hipError_t e = launch_fill_zero(h->gbuf(0), align_up(h->gbytes()), h->stream);
+  if (e == hipSuccess) e = launch_fill_zero(h->at<char>(L.stats), L.sponge - L.stats, h->stream);
+  if (e == hipSuccess) e = launch_fill_zero(h->at<char>(L.flag), kAlign, h->stream);
+  if (e == hipSuccess)
+    e = launch_sponge(h->at<float>(L.sponge), desc->nx, desc->periodic_x ? 0 : desc->sponge_cells,
+                      desc->sponge_K, desc->sponge_p, h->stream);
+  if (e != hipSuccess) {
+    const std::string msg = std::string("init kernels: ") + hipGetErrorString(e);
+    delete h;
+    return fail(nullptr, STGLBM_E_HIP, msg);
+  }
+  *out = h;
+  return STGLBM_OK;
+}
+
+int stglbm_set_rans_inlet(stglbm_t h, const stglbm_rans_inlet* in) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  if (h->d.periodic_x) return fail(h, STGLBM_E_STATE, "periodic_x lattice has no inlet");
+  if (!in || !in->y || !in->U3 || !in->k || !in->omega || !in->R6) return fail(h, STGLBM_E_INVAL, "null RANS input");
+  const int n = in->n_rans;
+  if (n < 2 || n > h->d.max_rans) return fail(h, STGLBM_E_INVAL, "n_rans out of range");
+  if (in->n_modes < 1 || in->n_modes > h->d.max_modes) return fail(h, STGLBM_E_INVAL, "n_modes out of range");
+  if (!(in->delta > 0) || !(in->c_x > 0) || !(in->c_t > 0) || !(in->U_b > 0) || !(in->nu_phys > 0) ||
+      !(in->C_l > 0) || !(in->C_mu > 0))
+    return fail(h, STGLBM_E_INVAL, "delta, c_x, c_t, U_b, nu_phys, C_l, C_mu must be positive");
+  if (std::fabs(in->c_x * h->d.ny - 2.0 * in->delta) > 1e-9 * in->delta)
+    return fail(h, STGLBM_E_INVAL, "c_x * NY must equal 2 delta");
+  if (!(in->y[0] > 0.0) || !(in->y[n - 1] < 2.0 * in->delta)) return fail(h, STGLBM_E_INVAL, "RANS y outside (0, 2 delta)");
+  for (int i = 1; i < n; ++i)
+    if (!(in->y[i] > in->y[i - 1])) return fail(h, STGLBM_E_INVAL, "RANS y must increase strictly");
+  for (int i = 0; i < n; ++i)
+    if (!(in->k[i] > 0.0) || !(in->omega[i] > 0.0)) return fail(h, STGLBM_E_INVAL, "k and omega must be positive");
+  if (in->n_modes == 1 && !(in->alpha > 0.0)) return fail(h, STGLBM_E_INVAL, "one mode needs alpha > 0");
+  int rc = sync_and_check(h);
+  if (rc != STGLBM_OK && rc != STGLBM_E_UNSTABLE) return rc;
+  // stage the RANS arrays: y[n] U3[n][3] k[n] omega[n] R6[n][6]
+  std::vector<double> stage(static_cast<size_t>(n) * 12);
+  std::memcpy(stage.data(), in->y, n * sizeof(double));
+  std::memcpy(stage.data() + n, in->U3, 3 * n * sizeof(double));
+  std::memcpy(stage.data() + 4 * n, in->k, n * sizeof(double));
+  std::memcpy(stage.data() + 5 * n, in->omega, n * sizeof(double));
+  std::memcpy(stage.data() + 6 * n, in->R6, 6 * n * sizeof(double));
+  double* dstage = h->at<double>(h->L.rans);
+  HIP_CHECK(h, hipMemcpyAsync(dstage, stage.data(), stage.size() * sizeof(double), hipMemcpyHostToDevice, h->stream),
+            "hipMemcpyAsync RANS");
+  SetupParams p{};
+  p.rans = dstage;
+  p.n_rans = n; p.ny = h->d.ny; p.nz = h->d.nz; p.n_modes = in->n_modes;
+  p.delta = in->delta; p.nu_phys = in->nu_phys; p.c_x = in->c_x; p.alpha = in->alpha;
+  p.C_l = in->C_l; p.C_mu = in->C_mu; p.U_b = in->U_b; p.seed = in->seed;
+  p.rows = h->at<double>(h->L.rows);
+  p.modes = h->at<double>(h->L.modes);
+  p.sqrtq = h->at<double>(h->L.sqrtq);
+  p.bz = h->at<float2>(h->L.bz);
+  p.sig = h->at<float4>(h->L.sig);
+  p.scalars = h->at<double>(h->L.scalars);
+  p.clamps = h->at<int>(h->L.flag) + 1;
+  HIP_CHECK(h, launch_inlet_setup(p, h->stream), "inlet setup kernels");
+  HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  double sc[kScalars];
+  HIP_CHECK(h, hipMemcpy(sc, p.scalars, sizeof(sc), hipMemcpyDeviceToHost), "hipMemcpy scalars");
+  if (in->strict && sc[5] > 0) return fail(h, STGLBM_E_REALIZABILITY, "negative Cholesky radicand (Reynolds stress not realizable)");
+  if (!(sc[0] > 0.0) || !std::isfinite(sc[0]) || !std::isfinite(sc[3]))
+    return fail(h, STGLBM_E_INVAL, "degenerate inlet length scales");
+  h->n_modes = in->n_modes;
+  h->c_x = in->c_x; h->c_t = in->c_t; h->U_b = in->U_b; h->L_e = sc[0];
+  uint64_t hs = 0xcbf29ce484222325ull;
+  hs = fnv1a(hs, stage.data(), stage.size() * sizeof(double));
+  const double params[] = {in->delta, in->nu_phys, in->c_x, in->c_t, in->U_b, in->alpha, in->C_l, in->C_mu};
+  hs = fnv1a(hs, params, sizeof(params));
+  hs = fnv1a(hs, &in->seed, sizeof(in->seed));
+  hs = fnv1a(hs, &in->n_modes, sizeof(in->n_modes));
+  h->inlet_hash = hs;
+  h->inlet_ready = true;
+  return rc;
+}
+
+int stglbm_stg_generate(stglbm_t h, int64_t t_step, float* d_u_plane) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  if (h->d.periodic_x || !h->inlet_ready) return fail(h, STGLBM_E_STATE, "no inlet installed");
+  return launch_plane(h, t_step, d_u_plane);
+}
+
+int stglbm_step(stglbm_t h, int32_t n_steps) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  if (n_steps < 0) return fail(h, STGLBM_E_INVAL, "n_steps < 0");
+  if (!h->d.periodic_x && !h->inlet_ready) return fail(h, STGLBM_E_STATE, "set_rans_inlet must precede step");
+  for (int32_t s = 0; s < n_steps; ++s) {
+    if (!h->d.periodic_x) {
+      const int rc = launch_plane(h, h->t + 1, nullptr);
+      if (rc) return rc;
+    }
+    StepParams p = step_params(h);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->prof) {
+      e0 = pooled_event(h->ev_step, 2 * h->n_step);
+      e1 = pooled_event(h->ev_step, 2 * h->n_step + 1);
+      if (e0 && e1) HIP_CHECK(h, hipEventRecord(e0, h->stream), "hipEventRecord");
+    }
+    HIP_CHECK(h, launch_step(p, h->d.store, h->sampling, h->stream), "step kernel launch");
+    if (h->prof && e0 && e1) {
+      HIP_CHECK(h, hipEventRecord(e1, h->stream), "hipEventRecord");
+      ++h->n_step;
+    }
+    h->cur = 1 - h->cur;
+    ++h->t;
+    if (h->sampling) ++h->n_samples;
+  }
+  return STGLBM_OK;
+}
+
+int stglbm_stats_reset(stglbm_t h) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  HIP_CHECK(h, launch_fill_zero(h->at<char>(h->L.stats), h->L.sponge - h->L.stats, h->stream), "stats reset");
+  h->n_samples = 0;
+  h->sampling = true;
+  return STGLBM_OK;
+}
+
+int stglbm_stats_stop(stglbm_t h) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  h->sampling = false;
+  return STGLBM_OK;
+}
+
+int stglbm_get_stats(stglbm_t h, double* h_out, uint64_t n, int64_t* n_samples) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  const uint64_t bins = static_cast<uint64_t>(h->d.nx) * h->d.ny;
+  if (!h_out || n != bins * 9) return fail(h, STGLBM_E_INVAL, "stats buffer must hold NX*NY*9 doubles");
+  const int rc = sync_and_check(h);
+  std::vector<double> raw(static_cast<size_t>(h->L.slots) * 9 * bins);
+  HIP_CHECK(h, hipMemcpy(raw.data(), h->at<double>(h->L.stats), raw.size() * sizeof(double), hipMemcpyDeviceToHost),
+            "hipMemcpy stats");
+  // device layout [slot][k][y][x]; API layout [x][y][k]; slots summed in order
+  for (int x = 0; x < h->d.nx; ++x)
+    for (int y = 0; y < h->d.ny; ++y)
+      for (int k = 0; k < 9; ++k) {
+        double v = 0.0;
+        for (int s = 0; s < h->L.slots; ++s) v += raw[(static_cast<size_t>(s) * 9 + k) * bins + static_cast<size_t>(y) * h->d.nx + x];
+        h_out[(static_cast<size_t>(x) * h->d.ny + y) * 9 + k] = v;
+      }
+  if (n_samples) *n_samples = h->n_samples;
+  return rc;
+}
+
+int stglbm_get_f(stglbm_t h, double* h_out, uint64_t n) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  const uint64_t total = static_cast<uint64_t>(kQ) * h->cells();
+  if (!h_out || n != total) return fail(h, STGLBM_E_INVAL, "f buffer must hold 19*NX*NY*NZ doubles");
+  const int rc = sync_and_check(h);
+  double* stage = static_cast<double*>(h->gbuf(1 - h->cur));
+  const uint64_t chunk = h->gbytes() / sizeof(double);
+  for (uint64_t off = 0; off < total; off += chunk) {
+    const uint64_t cnt = std::min<uint64_t>(chunk, total - off);
+    HIP_CHECK(h, launch_export_f(h->gbuf(h->cur), h->d.store, off, cnt, h->cells(), stage, h->stream), "export kernel");
+    HIP_CHECK(h, hipMemcpyAsync(h_out + off, stage, cnt * sizeof(double), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync f");
+    HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  }
+  return rc;
+}
+
+int stglbm_get_f_planes(stglbm_t h, int32_t x0, int32_t x1, double* h_out, uint64_t n) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  if (x0 < 0 || x1 > h->d.nx || x1 <= x0) return fail(h, STGLBM_E_INVAL, "need 0 <= x0 < x1 <= NX");
+  const uint64_t total = static_cast<uint64_t>(kQ) * h->d.nz * h->d.ny * (x1 - x0);
+  if (!h_out || n != total) return fail(h, STGLBM_E_INVAL, "buffer must hold 19*NZ*NY*(x1-x0) doubles");
+  if (total * sizeof(double) > h->gbytes()) return fail(h, STGLBM_E_INVAL, "plane range larger than the staging buffer");
+  const int rc = sync_and_check(h);
+  double* stage = static_cast<double*>(h->gbuf(1 - h->cur));
+  HIP_CHECK(h, launch_export_planes(h->gbuf(h->cur), h->d.store, h->d.nx, h->d.ny, h->d.nz, x0, x1, stage, h->stream),
+            "export kernel");
+  HIP_CHECK(h, hipMemcpyAsync(h_out, stage, total * sizeof(double), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync f");
+  HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return rc;
+}
+
+int stglbm_state_view(stglbm_t h, void** d_g, uint64_t* bytes) {
+  if (!h || !d_g || !bytes) return fail(h, STGLBM_E_INVAL, "null argument");
+  *d_g = h->gbuf(h->cur);
+  *bytes = h->gbytes();
+  return STGLBM_OK;
+}
+
+int stglbm_set_f(stglbm_t h, const double* h_in, uint64_t n) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  const uint64_t total = static_cast<uint64_t>(kQ) * h->cells();
+  if (!h_in || n != total) return fail(h, STGLBM_E_INVAL, "f buffer must hold 19*NX*NY*NZ doubles");
+  const int rc = sync_and_check(h);
+  if (rc != STGLBM_OK && rc != STGLBM_E_UNSTABLE) return rc;
+  double* stage = static_cast<double*>(h->gbuf(1 - h->cur));
+  const uint64_t chunk = h->gbytes() / sizeof(double);
+  for (uint64_t off = 0; off < total; off += chunk) {
+    const uint64_t cnt = std::min<uint64_t>(chunk, total - off);
+    HIP_CHECK(h, hipMemcpyAsync(stage, h_in + off, cnt * sizeof(double), hipMemcpyHostToDevice, h->stream), "hipMemcpyAsync f");
+    HIP_CHECK(h, launch_import_f(stage, h->d.store, off, cnt, h->cells(), h->gbuf(h->cur), h->stream), "import kernel");
+    HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  }
+  HIP_CHECK(h, launch_fill_zero(h->at<char>(h->L.flag), kAlign, h->stream), "flag reset");
+  HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return STGLBM_OK;
+}
+
+static int copy_out(stglbm_t h, uint64_t off, uint64_t bytes, double* out) {
+  const int rc = sync_and_check(h);
+  HIP_CHECK(h, hipMemcpy(out, h->ws + off, bytes, hipMemcpyDeviceToHost), "hipMemcpy");
+  return rc;
+}
+
+int stglbm_get_modes(stglbm_t h, double* h_out, uint64_t n) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  if (!h->inlet_ready) return fail(h, STGLBM_E_STATE, "no inlet installed");
+  if (!h_out || n != static_cast<uint64_t>(h->n_modes) * kModeFields) return fail(h, STGLBM_E_INVAL, "modes buffer must hold N*8 doubles");
+  return copy_out(h, h->L.modes, n * sizeof(double), h_out);
+}
+
+int stglbm_get_inlet_rows(stglbm_t h, double* h_out, uint64_t n) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  if (!h->inlet_ready) return fail(h, STGLBM_E_STATE, "no inlet installed");
+  if (!h_out || n != static_cast<uint64_t>(h->d.ny) * kRowFields) return fail(h, STGLBM_E_INVAL, "rows buffer must hold NY*18 doubles");
+  return copy_out(h, h->L.rows, n * sizeof(double), h_out);
+}
+
+int stglbm_get_inlet_scalars(stglbm_t h, double* h_out, uint64_t n) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  if (!h->inlet_ready) return fail(h, STGLBM_E_STATE, "no inlet installed");
+  if (!h_out || n != kScalars) return fail(h, STGLBM_E_INVAL, "scalars buffer must hold 8 doubles");
+  return copy_out(h, h->L.scalars, n * sizeof(double), h_out);
+}
+
+int stglbm_get_sqrtq(stglbm_t h, double* h_out, uint64_t n) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  if (!h->inlet_ready) return fail(h, STGLBM_E_STATE, "no inlet installed");
+  if (!h_out || n != static_cast<uint64_t>(h->d.ny) * h->n_modes) return fail(h, STGLBM_E_INVAL, "sqrtq buffer must hold NY*N doubles");
+  return copy_out(h, h->L.sqrtq, n * sizeof(double), h_out);
+}
+
+int stglbm_get_step(stglbm_t h, int64_t* t) {
+  if (!h || !t) return fail(h, STGLBM_E_INVAL, "null argument");
+  *t = h->t;
+  return STGLBM_OK;
+}
+
+int stglbm_set_stream(stglbm_t h, void* hip_stream) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  return STGLBM_OK;
+}
+
+int stglbm_sync(stglbm_t h) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  return sync_and_check(h);
+}
+
+int stglbm_checkpoint_size(stglbm_t h, uint64_t* bytes) {
+  if (!h || !bytes) return fail(h, STGLBM_E_INVAL, "null argument");
+  *bytes = sizeof(CkptHeader) + h->gbytes() + (h->L.sponge - h->L.stats);
+  return STGLBM_OK;
+}
+
+int stglbm_checkpoint(stglbm_t h, void* h_buf, uint64_t n) {
+  uint64_t need = 0;
+  if (int rc = stglbm_checkpoint_size(h, &need)) return rc;
+  if (!h_buf || n < need) return fail(h, STGLBM_E_INVAL, "checkpoint buffer too small");
+  const int rc = sync_and_check(h);
+  if (rc != STGLBM_OK) return rc;
+  CkptHeader hd{};
+  hd.magic = kCkptMagic; hd.version = kCkptVersion;
+  hd.nx = h->d.nx; hd.ny = h->d.ny; hd.nz = h->d.nz; hd.store = h->d.store; hd.periodic_x = h->d.periodic_x;
+  hd.slots = h->L.slots; hd.inlet_hash = h->inlet_hash; hd.t = h->t; hd.n_samples = h->n_samples;
+  hd.sampling = h->sampling ? 1 : 0; hd.n_modes = h->n_modes;
+  hd.g_bytes = h->gbytes(); hd.stats_bytes = h->L.sponge - h->L.stats;
+  char* out = static_cast<char*>(h_buf);
+  std::memcpy(out, &hd, sizeof(hd));
+  HIP_CHECK(h, hipMemcpy(out + sizeof(hd), h->gbuf(h->cur), hd.g_bytes, hipMemcpyDeviceToHost), "hipMemcpy g");
+  HIP_CHECK(h, hipMemcpy(out + sizeof(hd) + hd.g_bytes, h->ws + h->L.stats, hd.stats_bytes, hipMemcpyDeviceToHost), "hipMemcpy stats");
+  return STGLBM_OK;
+}
+
+int stglbm_restore(stglbm_t h, const void* h_buf, uint64_t n) {
+  if (!h || !h_buf) return fail(h, STGLBM_E_INVAL, "null argument");
+  if (n < sizeof(CkptHeader)) return fail(h, STGLBM_E_INVAL, "checkpoint too short");
+  CkptHeader hd;
+  std::memcpy(&hd, h_buf, sizeof(hd));
+  if (hd.magic != kCkptMagic || hd.version != kCkptVersion) return fail(h, STGLBM_E_INVAL, "not a checkpoint of this library");
+  if (hd.nx != h->d.nx || hd.ny != h->d.ny || hd.nz != h->d.nz || hd.store != h->d.store ||
+      hd.periodic_x != h->d.periodic_x || hd.slots != h->L.slots)
+    return fail(h, STGLBM_E_INVAL, "checkpoint lattice differs from the handle's");
+  if (!h->d.periodic_x && (!h->inlet_ready || hd.inlet_hash != h->inlet_hash || hd.n_modes != h->n_modes))
+    return fail(h, STGLBM_E_STATE, "install the same inlet (set_rans_inlet) before restoring");
+  if (n < sizeof(hd) + hd.g_bytes + hd.stats_bytes || hd.g_bytes != h->gbytes() ||
+      hd.stats_bytes != h->L.sponge - h->L.stats)
+    return fail(h, STGLBM_E_INVAL, "checkpoint size mismatch");
+  HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  const char* in = static_cast<const char*>(h_buf);
+  HIP_CHECK(h, hipMemcpy(h->gbuf(h->cur), in + sizeof(hd), hd.g_bytes, hipMemcpyHostToDevice), "hipMemcpy g");
+  HIP_CHECK(h, hipMemcpy(h->ws + h->L.stats, in + sizeof(hd) + hd.g_bytes, hd.stats_bytes, hipMemcpyHostToDevice), "hipMemcpy stats");
+  HIP_CHECK(h, launch_fill_zero(h->at<char>(h->L.flag), kAlign, h->stream), "flag reset");
+  HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  h->t = hd.t;
+  h->n_samples = hd.n_samples;
+  h->sampling = hd.sampling != 0;
+  return STGLBM_OK;
+}
+
+int stglbm_profile(stglbm_t h, int32_t enable) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  h->prof = enable != 0;
+  return STGLBM_OK;
+}
+
+int stglbm_profile_read(stglbm_t h, double* out, uint64_t n) {
+  if (!h || !out || n < 4) return fail(h, STGLBM_E_INVAL, "profile buffer must hold 4 doubles");
+  HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  double ms_step = 0.0, ms_stg = 0.0;
+  for (size_t i = 0; i < h->n_step; ++i) {
+    float ms = 0.f;
+    HIP_CHECK(h, hipEventElapsedTime(&ms, h->ev_step[2 * i], h->ev_step[2 * i + 1]), "hipEventElapsedTime");
+    ms_step += ms;
+  }
+  for (size_t i = 0; i < h->n_stg; ++i) {
+    float ms = 0.f;
+    HIP_CHECK(h, hipEventElapsedTime(&ms, h->ev_stg[2 * i], h->ev_stg[2 * i + 1]), "hipEventElapsedTime");
+    ms_stg += ms;
+  }
+  out[0] = ms_step; out[1] = static_cast<double>(h->n_step);
+  out[2] = ms_stg; out[3] = static_cast<double>(h->n_stg);
+  h->n_step = h->n_stg = 0;
+  return STGLBM_OK;
+}
+
+int stglbm_copy_probe(const void* d_src, void* d_dst, uint64_t bytes, void* hip_stream) {
+  if (!d_src || !d_dst || bytes % 16) return fail(nullptr, STGLBM_E_INVAL, "copy_probe needs non-null buffers and bytes % 16 == 0");
+  const hipError_t e = launch_copy(d_src, d_dst, bytes, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(nullptr, STGLBM_E_HIP, std::string("copy kernel: ") + hipGetErrorString(e));
+  return STGLBM_OK;
+}
+
+int stglbm_destroy(stglbm_t h) {
+  if (!h) return STGLBM_OK;
+  if (h->stream || true) (void)hipStreamSynchronize(h->stream);
+  for (hipEvent_t e : h->ev_step) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->ev_stg) (void)hipEventDestroy(e);
+  delete h;
+  return STGLBM_OK;
+}
+
+const char* stglbm_last_error(stglbm_t h) { return h ? h->err.c_str() : g_lib_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,463 @@
+// Lattice kernels of libstglbm: the fused stream-collide pass and its helpers.
+//
+// One launch advances every cell by one time step (Algorithm 1, step 12, with
+// the boundary steps 9-11 fused in): pull streaming with halfway bounce-back at
+// the y walls and spanwise wrap, the regularized rebuild of the inlet (x = 0)
+// and pressure-outlet (x = NX-1) nodes, the moments (eqs. density, momentum,
+// tensor), the Smagorinsky relaxation time (eqs. strain, tau_eff), the sponge
+// multiplier (eq. sponge_visco), the regularized BGK collision with the Guo
+// force (eqs. lbe, local_eq, bodyforce) and, while sampling, the FP64 flow
+// statistics.  The distributions live as deviations g_i = f_i - w_i so the
+// moments are sums of small numbers; arithmetic is FP32.
+//
+// Mapping: a wave owns 64 consecutive x cells of one (y, z) row, so each of the
+// 19 population loads and stores of a wave is one contiguous 256-byte (FP32)
+// or 128-byte (FP16/BF16) segment.  A block is 4 waves at the same (x tile, y)
+// stepping through a spanwise range, so the per-cell statistics reduce over z
+// in registers and then across the 4 waves in LDS before a single FP64
+// read-modify-write per (x, y) bin and block: fixed order, no atomics.  Blocks
+// are renumbered so that consecutive x tiles run on the same XCD, where the
+// cache lines straddled by the +-1 x shifts are shared through its L2.
+#include "stglbm_internal.h"
+
+namespace stglbm {
+namespace {
+
+// D3Q19 velocity set in the library's population order.
+__constant__ constexpr int CX[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__constant__ constexpr int CY[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+__constant__ constexpr int CZ[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+__constant__ constexpr int OPPOSITE[kQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+
+__host__ __device__ constexpr double weight_d(int i) {
+  return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+// w_i = weight_hi + weight_lo to ~2^-48 relative (float-float pair).
+__host__ __device__ constexpr float weight_hi(int i) { return static_cast<float>(weight_d(i)); }
+__host__ __device__ constexpr float weight_lo(int i) {
+  return static_cast<float>(weight_d(i) - static_cast<double>(weight_hi(i)));
+}
+// Adding and subtracting 12 rounds |g| < 4 to a multiple of 2^-20 (ulp of [8, 16)).
+constexpr float kSplit = 12.0f;
+
+// Storage codecs: FP32 as is; FP16 and BF16 as raw 16-bit words, rounded to
+// nearest even on encode, exact on decode.
+struct CodecF32 {
+  using storage = float;
+  static __device__ __forceinline__ float decode(float v) { return v; }
+  static __device__ __forceinline__ float encode(float v) { return v; }
+};
+struct CodecF16 {
+  using storage = unsigned short;
+  static __device__ __forceinline__ float decode(unsigned short v) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, v));
+  }
+  static __device__ __forceinline__ unsigned short encode(float v) {
+    return __builtin_bit_cast(unsigned short, static_cast<_Float16>(v));
+  }
+};
+struct CodecBF16 {
+  using storage = unsigned short;
+  static __device__ __forceinline__ float decode(unsigned short v) {
+    return __uint_as_float(static_cast<unsigned int>(v) << 16);
+  }
+  static __device__ __forceinline__ unsigned short encode(float v) {
+    unsigned int u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return static_cast<unsigned short>((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                                                             // nearest even
+    return static_cast<unsigned short>(u >> 16);
+  }
+};
+
+// Regularized rebuild of a boundary node (eqs. f_i, f_i_neq, pi_neq,
+// unknown_neq, bc_eq): SIGN is the c_x of the unknown (entering) populations.
+// On the known set f_neq = g - g_eq(rho, u); unknown ones mirror their opposite;
+// then g_i = g_eq_i + w_i/(2 c_s^4) Q_i : Pi_neq for every i.
+// w_i * S with w_i = weight_hi + weight_lo, one rounding and no systematic bias.
+__device__ __forceinline__ float wmul(int i, float S) { return __builtin_fmaf(weight_hi(i), S, weight_lo(i) * S); }
+
+// Regularized rebuild of a boundary node (eqs. f_i, f_i_neq, pi_neq,
+// unknown_neq, bc_eq): SIGN is the c_x of the unknown (entering) populations.
+// On the known set f_neq = g - g_eq(rho, u); unknown ones mirror their opposite;
+// then g_i = g_eq_i + w_i/(2 c_s^4) Q_i : Pi_neq for every i.
+template <int SIGN>
+__device__ __forceinline__ void regularized_rebuild(float (&g)[kQ], float drho, float ux, float uy, float uz) {
+  const float rho = 1.0f + drho;
+  const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+  float seq[kQ], fneq[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+    seq[i] = drho + rho * (3.0f * cu + 4.5f * cu * cu - uu15);   // g_eq_i / w_i
+  }
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) fneq[i] = g[i] - wmul(i, seq[i]);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i)
+    if (CX[i] == SIGN) fneq[i] = fneq[OPPOSITE[i]];
+  float pxx = 0.f, pyy = 0.f, pzz = 0.f, pxy = 0.f, pxz = 0.f, pyz = 0.f;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    pxx += (CX[i] * CX[i]) * fneq[i];
+    pyy += (CY[i] * CY[i]) * fneq[i];
+    pzz += (CZ[i] * CZ[i]) * fneq[i];
+    pxy += (CX[i] * CY[i]) * fneq[i];
+    pxz += (CX[i] * CZ[i]) * fneq[i];
+    pyz += (CY[i] * CZ[i]) * fneq[i];
+  }
+  const float tr3 = (pxx + pyy + pzz) * (1.0f / 3.0f);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const float qp = (CX[i] * CX[i]) * pxx + (CY[i] * CY[i]) * pyy + (CZ[i] * CZ[i]) * pzz +
+                     2.0f * ((CX[i] * CY[i]) * pxy + (CX[i] * CZ[i]) * pxz + (CY[i] * CZ[i]) * pyz) - tr3;
+    g[i] = wmul(i, seq[i] + 4.5f * qp);
+  }
+}
+
+template <class Codec, bool STATS>
+__global__ __launch_bounds__(64 * kWavesZ) void step_kernel(StepParams p) {
+  using S = typename Codec::storage;
+  const S* __restrict__ gin = static_cast<const S*>(p.gin);
+  S* __restrict__ gout = static_cast<S*>(p.gout);
+  const int lane = threadIdx.x;
+  const int wz = threadIdx.y;
+  int b = blockIdx.x;
+  if (p.remap) {
+    const int per = p.nblocks >> 3;
+    b = (b & 7) * per + (b >> 3);
+  }
+  const int xt = b % p.nxt;
+  const int rest = b / p.nxt;
+  const int y = rest % p.ny;
+  const int slot = rest / p.ny;
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const long long plane = p.plane;
+  const int x = xt * 64 + lane;
+  const bool active = x < nx;
+  const int xc = active ? x : nx - 1;
+  int xm = xc - 1, xp = xc + 1;
+  if (p.periodic_x) {
+    xm = xm < 0 ? nx - 1 : xm;
+    xp = xp >= nx ? 0 : xp;
+  } else {
+    xm = xm < 0 ? 0 : xm;               // entering through the inlet: rebuilt
+    xp = xp >= nx ? nx - 1 : xp;        // entering through the outlet: rebuilt
+  }
+  const bool inlet = !p.periodic_x && x == 0;
+  const bool outlet = !p.periodic_x && x == nx - 1;
+  const float sp = p.sponge[xc];
+
+  float acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
+  int bad = 0;
+
+  const int z0 = slot * kWavesZ * p.lw + wz;
+  for (int it = 0; it < p.lw; ++it) {
+    const int z = z0 + it * kWavesZ;
+    if (z >= nz) break;
+    const int zm = z == 0 ? nz - 1 : z - 1;
+    const int zp = z == nz - 1 ? 0 : z + 1;
+    const int here = (z * ny + y) * nx + xc;
+
+    // pull streaming: g_i(x) <- g_i(x - c_i); bounce-back g_opp(i)(x) behind a wall
+    float g[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const int ys = y - CY[i];
+      const bool wall = ys < 0 || ys >= ny;
+      const int zs = CZ[i] == 0 ? z : (CZ[i] > 0 ? zm : zp);
+      const int xs = CX[i] == 0 ? xc : (CX[i] > 0 ? xm : xp);
+      const int pop = wall ? OPPOSITE[i] : i;
+      const int off = wall ? here : (zs * ny + ys) * nx + xs;
+      g[i] = Codec::decode(gin[pop * plane + off]);
+    }
+
+    if (inlet) {
+      const float* u = p.ubc + 3 * (y * nz + z);
+      const float ux = u[0], uy = u[1], uz = u[2];
+      float g0 = 0.f, gm = 0.f;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) {
+        if (CX[i] == 0) g0 += g[i];
+        if (CX[i] == -1) gm += g[i];
+      }
+      // Zou-He (eq. density_bc): rho (1 - u_x) = sum_{c_x=0} f + 2 sum_{c_x=-1} f
+      const float drho = (g0 + 2.0f * gm + ux) / (1.0f - ux);
+      regularized_rebuild<1>(g, drho, ux, uy, uz);
+    } else if (outlet) {
+      float g0 = 0.f, gp = 0.f;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) {
+        if (CX[i] == 0) g0 += g[i];
+        if (CX[i] == 1) gp += g[i];
+      }
+      // rho_out (1 + u_x) = sum_{c_x=0} f + 2 sum_{c_x=+1} f, tangential u = 0
+      const float ux = (g0 + 2.0f * gp - p.rho_out_m1) * p.inv_rho_out;
+      regularized_rebuild<-1>(g, p.rho_out_m1, ux, 0.0f, 0.0f);
+    }
+
+    // Moments as exact integer combinations of the g_i.  Each g is split into
+    // hi (g rounded to a multiple of 2^-20, so sums of hi are exact in FP32
+    // while |sum| < 16) and lo = g - hi (exact, |lo| <= 2^-21).
+    float dh = 0.f, dl = 0.f;                          // sum g
+    float jxh = 0.f, jxl = 0.f, jyh = 0.f, jyl = 0.f, jzh = 0.f, jzl = 0.f;   // sum c g
+    float hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;  // sum (3 c_a c_b - d_ab) g
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const float h = (g[i] + kSplit) - kSplit;
+      const float l = g[i] - h;
+      dh += h;
+      dl += l;
+      if (CX[i]) { jxh += CX[i] * h; jxl += CX[i] * l; }
+      if (CY[i]) { jyh += CY[i] * h; jyl += CY[i] * l; }
+      if (CZ[i]) { jzh += CZ[i] * h; jzl += CZ[i] * l; }
+      hxx += (3 * CX[i] * CX[i] - 1) * g[i];
+      hyy += (3 * CY[i] * CY[i] - 1) * g[i];
+      hzz += (3 * CZ[i] * CZ[i] - 1) * g[i];
+      if (CX[i] * CY[i]) hxy += (3 * CX[i] * CY[i]) * g[i];
+      if (CX[i] * CZ[i]) hxz += (3 * CX[i] * CZ[i]) * g[i];
+      if (CY[i] * CZ[i]) hyz += (3 * CY[i] * CZ[i]) * g[i];
+    }
+    const float drho = dh + dl;
+    const float rho = 1.0f + drho;
+    const float irho = 1.0f / rho;
+    // rho u = sum c f + F/2 (eq. momentum)
+    const float ux = ((jxh + jxl) + 0.5f * p.fx) * irho;
+    const float uy = ((jyh + jyl) + 0.5f * p.fy) * irho;
+    const float uz = ((jzh + jzl) + 0.5f * p.fz) * irho;
+    bad |= !(fabsf(drho) < 0.5f);
+
+    // Pi_neq = sum c c (f - f_eq) = sum (c c - c_s^2 I) g - rho u u
+    const float nxx = hxx * (1.0f / 3.0f) - rho * ux * ux;
+    const float nyy = hyy * (1.0f / 3.0f) - rho * uy * uy;
+    const float nzz = hzz * (1.0f / 3.0f) - rho * uz * uz;
+    const float nxy = hxy * (1.0f / 3.0f) - rho * ux * uy;
+    const float nxz = hxz * (1.0f / 3.0f) - rho * ux * uz;
+    const float nyz = hyz * (1.0f / 3.0f) - rho * uy * uz;
+    const float q2 = nxx * nxx + nyy * nyy + nzz * nzz + 2.0f * (nxy * nxy + nxz * nxz + nyz * nyz);
+    // tau_eff - 1/2 = (tau0 - 1/2) + X / (2 (sqrt(tau0^2 + X) + tau0)), X = 18 sqrt2 Cs^2 Q^1/2 / rho
+    const float X = p.c18 * sqrtf(q2) * irho;
+    const float s = (p.s0 + X / (2.0f * (sqrtf(p.tau0_sq + X) + p.tau0))) * sp;
+    const float itau = 1.0f / (0.5f + s);
+    const float omw = (s - 0.5f) * itau;      // 1 - 1/tau
+    const float omhw = s * itau;              // 1 - 1/(2 tau)
+    const float tr3 = (nxx + nyy + nzz) * (1.0f / 3.0f);
+    const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+    const float uF = ux * p.fx + uy * p.fy + uz * p.fz;
+
+    // g_i' = w_i [drho + 3 c_i.(rho u) + rho (4.5 (c_i.u)^2 - 1.5 u.u)
+    //             + (1 - 1/tau) (4.5 Q_i:Pi_neq - 1.5 c_i.F) + Guo source]
+    // with drho + 3 c_i.J summed exactly from the hi parts; w_i applied as
+    // w_hi S + w_lo S so the rounding of w_i leaves no systematic bias.
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+      const float qp = (CX[i] * CX[i]) * nxx + (CY[i] * CY[i]) * nyy + (CZ[i] * CZ[i]) * nzz +
+                       2.0f * ((CX[i] * CY[i]) * nxy + (CX[i] * CZ[i]) * nxz + (CY[i] * CZ[i]) * nyz) - tr3;
+      const float ah = dh + 3.0f * (CX[i] * jxh + CY[i] * jyh + CZ[i] * jzh);   // exact
+      const float al = dl + 3.0f * (CX[i] * jxl + CY[i] * jyl + CZ[i] * jzl);
+      float rest = rho * (4.5f * cu * cu - uu15) + omw * (4.5f * qp);
+      if (p.has_force) {
+        const float cF = CX[i] * p.fx + CY[i] * p.fy + CZ[i] * p.fz;
+        // 3 c.(F/2) from rho u, the relaxed first-order part -F/2, and Guo's source
+        rest += 1.5f * cF + omw * (-1.5f * cF) + omhw * (3.0f * (cF - uF) + 9.0f * cu * cF);
+      }
+      const float S = ah + (al + rest);
+      const float out = wmul(i, S);
+      if (active) __builtin_nontemporal_store(Codec::encode(out), &gout[i * plane + here]);
+    }
+
+    if (STATS) {
+      acc[0] += ux;
+      acc[1] += uy;
+      acc[2] += uz;
+      acc[3] += ux * ux;
+      acc[4] += uy * uy;
+      acc[5] += uz * uz;
+      acc[6] += ux * uy;
+      acc[7] += ux * uz;
+      acc[8] += uy * uz;
+    }
+  }
+
+  // one flag write per wave
+  if (__any(bad && active)) {
+    if (lane == 0) atomicOr(p.flag, kFlagDensity);
+  }
+
+  if (STATS) {
+    __shared__ float red[kWavesZ][9][64];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) red[wz][k][lane] = acc[k];
+    __syncthreads();
+    if (wz == 0 && active) {
+      const long long bin = (long long)y * nx + x;
+      const long long sstride = (long long)ny * nx;
+      double* st = p.stats + (long long)slot * 9 * sstride + bin;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        float v = red[0][k][lane];
+#pragma unroll
+        for (int w = 1; w < kWavesZ; ++w) v += red[w][k][lane];
+        st[k * sstride] += static_cast<double>(v);
+      }
+    }
+  }
+}
+
+__global__ void fill_zero_kernel(uint4* p, unsigned long long n16) {
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__global__ void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, unsigned long long n16) {
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    dst[i] = src[i];
+}
+
+// Sponge (eq. sponge_visco): nu_sponge = nu_eff (1 + K s^p), s = (x - x_s)/(x_e - x_s),
+// x_e = NX - 1, x_s = x_e - L_s; stored as the multiplier of tau - 1/2.
+__global__ void sponge_kernel(float* sponge, int nx, int cells, double K, double pw) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= nx) return;
+  double fac = 1.0;
+  if (cells > 0) {
+    const int x_end = nx - 1, x_start = x_end - cells;
+    if (x >= x_start) {
+      const double s = static_cast<double>(x - x_start) / static_cast<double>(x_end - x_start);
+      fac = K * pow(s, pw) + 1.0;
+    }
+  }
+  sponge[x] = static_cast<float>(fac);
+}
+
+template <class Codec>
+__global__ void export_f_kernel(const typename Codec::storage* g, long long offset, long long count,
+                                long long plane, double* out) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride) {
+    const long long e = offset + k;
+    const int i = static_cast<int>(e / plane);
+    out[k] = weight_d(i) + static_cast<double>(Codec::decode(g[e]));
+  }
+}
+
+template <class Codec>
+__global__ void export_planes_kernel(const typename Codec::storage* g, int nx, int ny, int nz, int x0, int w,
+                                     double* out) {
+  const long long count = (long long)kQ * nz * ny * w;
+  const long long plane = (long long)nx * ny * nz;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride) {
+    const int xx = static_cast<int>(k % w);
+    const long long r = k / w;                    // (i, z, y)
+    const int i = static_cast<int>(r / ((long long)nz * ny));
+    const long long zy = r % ((long long)nz * ny);
+    out[k] = weight_d(i) + static_cast<double>(Codec::decode(g[i * plane + zy * nx + x0 + xx]));
+  }
+}
+
+template <class Codec>
+__global__ void import_f_kernel(const double* f, long long offset, long long count, long long plane,
+                                typename Codec::storage* g) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride) {
+    const long long e = offset + k;
+    const int i = static_cast<int>(e / plane);
+    g[e] = Codec::encode(static_cast<float>(f[k] - weight_d(i)));
+  }
+}
+
+int grid_for(unsigned long long n, int block) {
+  unsigned long long b = (n + block - 1) / block;
+  if (b > 65536ull * 4) b = 65536ull * 4;
+  if (b < 1) b = 1;
+  return static_cast<int>(b);
+}
+
+}  // namespace
+
+hipError_t launch_step(const StepParams& p, int store, bool stats, hipStream_t s) {
+  const dim3 block(64, kWavesZ);
+  const dim3 grid(p.nblocks);
+  switch (store) {
+    case 0:
+      if (stats) step_kernel<CodecF32, true><<<grid, block, 0, s>>>(p);
+      else step_kernel<CodecF32, false><<<grid, block, 0, s>>>(p);
+      break;
+    case 1:
+      if (stats) step_kernel<CodecF16, true><<<grid, block, 0, s>>>(p);
+      else step_kernel<CodecF16, false><<<grid, block, 0, s>>>(p);
+      break;
+    case 2:
+      if (stats) step_kernel<CodecBF16, true><<<grid, block, 0, s>>>(p);
+      else step_kernel<CodecBF16, false><<<grid, block, 0, s>>>(p);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void* ptr, unsigned long long bytes, hipStream_t s) {
+  if (bytes % 16) return hipErrorInvalidValue;
+  const unsigned long long n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  fill_zero_kernel<<<grid_for(n16, 256), 256, 0, s>>>(static_cast<uint4*>(ptr), n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const void* src, void* dst, unsigned long long bytes, hipStream_t s) {
+  if (bytes % 16) return hipErrorInvalidValue;
+  const unsigned long long n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  copy_kernel<<<grid_for(n16, 256), 256, 0, s>>>(static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_sponge(float* sponge, int nx, int cells, double K, double pw, hipStream_t s) {
+  sponge_kernel<<<(nx + 255) / 256, 256, 0, s>>>(sponge, nx, cells, K, pw);
+  return hipGetLastError();
+}
+
+hipError_t launch_export_f(const void* g, int store, long long offset, long long count, long long plane,
+                           double* out, hipStream_t s) {
+  const int grid = grid_for(static_cast<unsigned long long>(count), 256);
+  switch (store) {
+    case 0: export_f_kernel<CodecF32><<<grid, 256, 0, s>>>(static_cast<const float*>(g), offset, count, plane, out); break;
+    case 1: export_f_kernel<CodecF16><<<grid, 256, 0, s>>>(static_cast<const unsigned short*>(g), offset, count, plane, out); break;
+    case 2: export_f_kernel<CodecBF16><<<grid, 256, 0, s>>>(static_cast<const unsigned short*>(g), offset, count, plane, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_export_planes(const void* g, int store, int nx, int ny, int nz, int x0, int x1, double* out,
+                               hipStream_t s) {
+  const int w = x1 - x0;
+  const int grid = grid_for(static_cast<unsigned long long>(kQ) * nz * ny * w, 256);
+  switch (store) {
+    case 0: export_planes_kernel<CodecF32><<<grid, 256, 0, s>>>(static_cast<const float*>(g), nx, ny, nz, x0, w, out); break;
+    case 1: export_planes_kernel<CodecF16><<<grid, 256, 0, s>>>(static_cast<const unsigned short*>(g), nx, ny, nz, x0, w, out); break;
+    case 2: export_planes_kernel<CodecBF16><<<grid, 256, 0, s>>>(static_cast<const unsigned short*>(g), nx, ny, nz, x0, w, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_import_f(const double* f, int store, long long offset, long long count, long long plane,
+                           void* g, hipStream_t s) {
+  const int grid = grid_for(static_cast<unsigned long long>(count), 256);
+  switch (store) {
+    case 0: import_f_kernel<CodecF32><<<grid, 256, 0, s>>>(f, offset, count, plane, static_cast<float*>(g)); break;
+    case 1: import_f_kernel<CodecF16><<<grid, 256, 0, s>>>(f, offset, count, plane, static_cast<unsigned short*>(g)); break;
+    case 2: import_f_kernel<CodecBF16><<<grid, 256, 0, s>>>(f, offset, count, plane, static_cast<unsigned short*>(g)); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace stglbm

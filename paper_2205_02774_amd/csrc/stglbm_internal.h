@@ -1,0 +1,90 @@
+// Internal declarations shared by the kernels and the C ABI of libstglbm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace stglbm {
+
+constexpr int kQ = 19;
+constexpr int kRowFields = 18;      // U(3) k omega R(6) a(6) l_e
+constexpr int kModeFields = 8;      // k, d(3), sigma(3), phi
+constexpr int kScalars = 8;         // L_e k_min k_max alpha k_cut clamps U_b N
+constexpr int kWavesZ = 4;          // waves per block of the step kernel (spanwise)
+constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel
+constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
+
+// Flag bits written by the kernels into the handle's status word.
+constexpr int kFlagDensity = 1;     // |rho - 1| >= 0.5 or NaN in the step kernel
+constexpr int kFlagInletMach = 2;   // |u_bc,x| >= 0.3 c_s at an inlet node
+
+// Fused stream-collide pass, one launch per time step.
+struct StepParams {
+  const void* gin;          // g at step n, [19][NZ][NY][NX] in the store type
+  void* gout;               // g at step n+1
+  long long plane;          // NX*NY*NZ
+  int nx, ny, nz;
+  int nxt;                  // number of 64-wide x tiles
+  int slots;                // spanwise blocks per (x tile, y); statistics slots
+  int lw;                   // spanwise cells per wave
+  int nblocks;
+  int remap;                // XCD-aware tile order (nblocks % 8 == 0)
+  int periodic_x;
+  int has_force;
+  float tau0, tau0_sq;      // tau0 and tau0^2 (rounded from FP64)
+  float s0;                 // tau0 - 1/2 (rounded from FP64)
+  float c18;                // 18 sqrt(2) Cs^2
+  float fx, fy, fz;         // Guo acceleration
+  float rho_out_m1;         // rho_out - 1
+  float inv_rho_out;        // 1/rho_out
+  const float* sponge;      // [NX] viscosity multipliers (all 1 if no sponge)
+  const float* ubc;         // [NY][NZ][3] inlet velocity (lattice units)
+  double* stats;            // [slots][9][NY][NX] FP64 sums
+  int* flag;
+};
+
+// STG inlet plane, one launch per time step.
+struct StgParams {
+  const double* modes;      // [N][8]
+  const double* sqrtq;      // [NY][N]
+  const float2* bz;         // [N][NZ] spanwise phasors exp(i k d_z z)
+  const float4* sig;        // [N] sigma^n in FP32 (x, y, z, 0)
+  const double* rows;       // [NY][18]
+  float* out;               // [NY][NZ][3]
+  int* flag;
+  int ny, nz, n_modes;
+  double c_x;               // lattice spacing (m)
+  double conv;              // c_t / c_x
+  double tphase;            // 2 pi (x_in - U_b t) / L_e for this step
+  float mach_limit;         // 0.3 c_s
+};
+
+// One-off inlet precompute.
+struct SetupParams {
+  const double* rans;       // staging: y[n] U3[n][3] k[n] omega[n] R6[n][6]
+  int n_rans, ny, nz, n_modes;
+  double delta, nu_phys, c_x, alpha, C_l, C_mu, U_b;
+  unsigned long long seed;
+  double* rows;             // [NY][18]
+  double* modes;            // [N][8]
+  double* sqrtq;            // [NY][N]
+  float2* bz;               // [N][NZ]
+  float4* sig;              // [N]
+  double* scalars;          // [8]
+  int* clamps;
+};
+
+hipError_t launch_step(const StepParams& p, int store, bool stats, hipStream_t s);
+hipError_t launch_stg(const StgParams& p, hipStream_t s);
+hipError_t launch_inlet_setup(const SetupParams& p, hipStream_t s);
+hipError_t launch_fill_zero(void* ptr, unsigned long long bytes, hipStream_t s);
+hipError_t launch_sponge(float* sponge, int nx, int cells, double K, double p, hipStream_t s);
+hipError_t launch_export_f(const void* g, int store, long long offset, long long count,
+                           long long plane, double* out, hipStream_t s);
+hipError_t launch_export_planes(const void* g, int store, int nx, int ny, int nz, int x0, int x1,
+                               double* out, hipStream_t s);
+hipError_t launch_import_f(const double* f, int store, long long offset, long long count,
+                           long long plane, void* g, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, unsigned long long bytes, hipStream_t s);
+
+}  // namespace stglbm

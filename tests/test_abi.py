@@ -1,0 +1,96 @@
+"""CPU checks of the C ABI: the library loads, exports what the header
+declares, the ctypes mirrors match the C struct layout, and the host-only
+logic (descriptor validation, footprint, unit derivation) behaves."""
+
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stglbm.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2205_02774_amd import abi
+    if not os.path.exists(abi.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return abi.load()
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(stglbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2205_02774_amd import abi
+    names = _declared()
+    assert len(names) >= 25
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(abi.EXPORTED) == names
+
+
+def test_struct_layout_matches_header():
+    """Compile a host-only C probe of sizeof/offsetof and compare with ctypes."""
+    from paper_2205_02774_amd import abi
+    fields = {
+        "stglbm_lattice_desc": [f[0] for f in abi.LatticeDesc._fields_],
+        "stglbm_rans_inlet": [f[0] for f in abi.RansInlet._fields_],
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "stglbm.h"', "int main(void){"]
+    for st, fl in fields.items():
+        lines.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fl:
+            lines.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0;}")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = dict(l.rsplit(" ", 1) for l in out.strip().splitlines())
+    for cls, st in ((abi.LatticeDesc, "stglbm_lattice_desc"), (abi.RansInlet, "stglbm_rans_inlet")):
+        assert int(got[st]) == ctypes.sizeof(cls)
+        for f, _ in cls._fields_:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, f
+
+
+def test_descriptor_validation_and_footprint(lib):
+    from paper_2205_02774_amd import abi, make_desc, footprint
+    d = make_desc(512, 128, 256, nu_lb=1.1458e-3, max_modes=600, max_rans=96)
+    fp = footprint(d)
+    assert fp >= 2 * 19 * 512 * 128 * 256 * 4
+    assert fp < 2 * 19 * 512 * 128 * 256 * 4 * 1.02
+    d16 = make_desc(512, 128, 256, nu_lb=1.1458e-3, store="f16", max_modes=600, max_rans=96)
+    assert footprint(d16) < 0.52 * fp
+    bad = make_desc(1, 128, 256, nu_lb=1e-3, max_modes=10, max_rans=10)
+    with pytest.raises(abi.StglbmError) as e:
+        footprint(bad)
+    assert e.value.code == abi.E_INVAL
+    with pytest.raises(abi.StglbmError):
+        footprint(make_desc(64, 32, 32, nu_lb=-1.0, max_modes=10, max_rans=10))
+    with pytest.raises(abi.StglbmError):
+        footprint(make_desc(64, 32, 32, nu_lb=1e-3, max_modes=0, max_rans=10))
+    # periodic lattices need no inlet tables
+    dp = make_desc(64, 32, 32, nu_lb=1e-3, periodic_x=True)
+    assert footprint(dp) < footprint(make_desc(64, 32, 32, nu_lb=1e-3, max_modes=50, max_rans=32))
+    # init without a workspace fails on the host before touching a device
+    h = ctypes.c_void_p()
+    rc = lib.stglbm_init_lattice(ctypes.byref(d), None, 0, None, ctypes.byref(h))
+    assert rc == abi.E_INVAL and not h.value
+
+
+def test_derive_units_matches_oracle(lib):
+    from paper_2205_02774_amd import derive_units
+    from oracle import units
+    got = derive_units(1.0, 128, 0.05, 15.37, 1 / 180)
+    c_x, c_t, nu_lb, _ = units.channel_units(1.0, 128, 0.05, 15.37, 1 / 180)
+    assert got == pytest.approx((c_x, c_t, nu_lb), rel=1e-15)

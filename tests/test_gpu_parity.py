@@ -1,0 +1,293 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances.  The path computes in FP32 on deviations g = f - w.  Per step
+each stored g_i carries a rounding of ~6e-8 |g_i| and the moments a few
+ulps of sums of |g| ~ 1e-2 w_i, so f moves by ~1e-9 relative per step; the
+FP32 bar for f after 100-200 steps is the 1e-6 relative error that the
+method's FP32 target states.  Precompute tables are FP64 on both sides
+(1e-12).  The inlet plane is an FP32 sum of N products of FP32-rounded
+phasors: bounded by ~N 2^-24 sum |terms| ~ 1e-6 of its magnitude.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import OracleChannel
+from oracle.stg import InletGenerator
+from workloads import channel_config, perturbed_state
+from workloads.configs import small_channel
+
+pytestmark = pytest.mark.gpu
+
+FP32_F_TOL = 1e-6
+
+
+def _lat(cfg, **kw):
+    from paper_2205_02774_amd import channel_from_config
+    print(f"[gpu] case {cfg['name']} {kw}", flush=True)
+    return channel_from_config(cfg, device="cuda:0", **kw)
+
+
+def _rel(a, b):
+    return np.abs(a - b) / np.abs(b)
+
+
+def _oracle_inlet(cfg):
+    """The oracle's inlet generator alone (no lattice arrays), units derived by the oracle."""
+    from oracle import units
+    rans = cfg["rans"]
+    c_x, c_t, _, _ = units.channel_units(cfg["delta"], cfg["ny"], cfg["u_b_lb"], rans["U_b"], cfg["nu_phys"])
+    return InletGenerator(rans, cfg["ny"], cfg["nz"], cfg["delta"], c_x, c_t, cfg["nu_phys"], rans["U_b"],
+                          cfg["n_modes"], cfg["alpha"], cfg["seed"], cfg["C_l"], cfg["C_mu"])
+
+
+@pytest.mark.parametrize("cfg_index", [0, 1, 3])
+def test_inlet_precompute_parity(cfg_index):
+    cfg = channel_config(cfg_index)
+    lat = _lat(cfg)
+    ora = _oracle_inlet(cfg)
+    rows = lat.get_inlet_rows()
+    np.testing.assert_allclose(rows[:, 0:3], ora.U_int, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(rows[:, 3], ora.k, rtol=1e-12)
+    np.testing.assert_allclose(rows[:, 4], ora.omega, rtol=1e-12)
+    np.testing.assert_allclose(rows[:, 5:11], ora.R6, rtol=1e-12, atol=1e-15)
+    a = ora.a
+    np.testing.assert_allclose(rows[:, 11:17],
+                               np.stack([a[:, 0, 0], a[:, 1, 0], a[:, 1, 1], a[:, 2, 0], a[:, 2, 1], a[:, 2, 2]], 1),
+                               rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(rows[:, 17], ora.l_e, rtol=1e-13)
+    sc = lat.get_inlet_scalars()
+    np.testing.assert_allclose(sc[:5], [ora.L_e, ora.k_min, ora.k_max, ora.alpha, ora.k_cut.max()], rtol=1e-13)
+    assert sc[5] == ora.clamps == 0
+    np.testing.assert_allclose(lat.get_modes(), ora.modes_table(), rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(lat.get_sqrtq(), np.sqrt(ora.q), rtol=1e-11, atol=1e-300)
+    lat.close()
+
+
+@pytest.mark.parametrize("cfg_index", [0, 1])
+def test_stg_plane_parity(cfg_index):
+    cfg = channel_config(cfg_index)
+    lat = _lat(cfg)
+    ora = _oracle_inlet(cfg)
+    for t in (1, 137, 20_000):
+        u_gpu = lat.stg_generate(t).cpu().numpy().astype(np.float64)
+        u_ora = ora.plane(t)
+        scale = np.abs(u_ora).max()
+        err = np.abs(u_gpu - u_ora).max() / scale
+        print(f"[gpu] plane t={t}: max abs err / max|u| = {err:.3e}", flush=True)
+        assert err < 1e-6
+    lat.close()
+
+
+def _periodic_pair(nx, ny, nz, store="f32", cs=0.1, force=(2e-6, 0.0, 0.0), nu=1e-3, seed=0):
+    from paper_2205_02774_amd import Lattice
+    lat = Lattice(nx, ny, nz, device="cuda:0", store=store, periodic_x=True, nu_lb=nu, cs_smag=cs, force=force)
+    ora = OracleChannel(nx, ny, nz, nu_lb=nu, cs_smag=cs, force=force, periodic_x=True)
+    f0 = ora.f + perturbed_state(nx, ny, nz, seed=seed, amplitude=2e-2)
+    ora.set_f(f0)
+    lat.set_f(f0)
+    return lat, ora
+
+
+@pytest.mark.parametrize("shape", [(64, 32, 16), (37, 9, 5), (130, 6, 3)])
+def test_periodic_channel_parity(shape):
+    """Periodic x, walls, Smagorinsky, Guo force, perturbed start; ragged tiles included."""
+    print(f"[gpu] periodic {shape}", flush=True)
+    lat, ora = _periodic_pair(*shape)
+    # the FP32 import rounds the start; compare from the rounded state
+    ora.set_f(lat.get_f())
+    lat.stats_reset()
+    ora.stats_reset()
+    lat.step(100)
+    ora.step(100)
+    rel = _rel(lat.get_f(), ora.f)
+    print(f"[gpu] periodic {shape}: max rel err f after 100 steps = {rel.max():.3e}", flush=True)
+    assert rel.max() < FP32_F_TOL
+    st, ns = lat.get_stats()
+    assert ns == 100
+    nrm = np.linalg.norm(st - ora.stats) / np.linalg.norm(ora.stats)
+    print(f"[gpu] periodic {shape}: stats normwise rel err = {nrm:.3e}", flush=True)
+    assert nrm < 1e-6
+    lat.close()
+
+
+@pytest.mark.parametrize("steps", [100, 200])
+def test_channel_64x32x32_parity(steps):
+    """The 64x32x32 STG channel (inlet, outlet, sponge, walls) from rest."""
+    cfg = channel_config(0)
+    lat = _lat(cfg)
+    ora = OracleChannel.from_config(cfg)
+    lat.stats_reset()
+    ora.stats_reset()
+    lat.step(steps)
+    ora.step(steps)
+    f = lat.get_f()
+    rel = _rel(f, ora.f)
+    l2 = np.linalg.norm(f - ora.f) / np.linalg.norm(ora.f)
+    print(f"[gpu] channel-64x32x32 {steps} steps: max rel err {rel.max():.3e}, L2 rel err {l2:.3e}", flush=True)
+    assert rel.max() < FP32_F_TOL
+    st, ns = lat.get_stats()
+    assert ns == steps
+    nrm = np.linalg.norm(st - ora.stats) / np.linalg.norm(ora.stats)
+    mean_u = np.abs(st[..., 0] - ora.stats[..., 0]).max() / np.abs(ora.stats[..., 0]).max()
+    print(f"[gpu] stats normwise rel err {nrm:.3e}, mean-u rel err {mean_u:.3e}", flush=True)
+    assert nrm < 1e-6 and mean_u < 1e-6
+    lat.close()
+
+
+@pytest.mark.parametrize("shape", [(33, 10, 7), (70, 8, 5)])
+def test_ragged_inlet_channel_parity(shape):
+    nx, ny, nz = shape
+    cfg = small_channel(nx, ny, nz, n_modes=17, seed=5)
+    lat = _lat(cfg)
+    ora = OracleChannel.from_config(cfg)
+    lat.step(60)
+    ora.step(60)
+    rel = _rel(lat.get_f(), ora.f)
+    print(f"[gpu] ragged {shape}: max rel err {rel.max():.3e}", flush=True)
+    assert rel.max() < FP32_F_TOL
+    lat.close()
+
+
+@pytest.mark.parametrize("cfg_index,steps", [(1, 8), (3, 4)])
+def test_full_size_front_parity(cfg_index, steps):
+    """Full-size lattice in the bench's launch shape, checked where the oracle can follow it.
+
+    From rest, information moves one cell per step, so after K steps only the
+    planes x <= K differ from rest; an oracle channel of 2K + 2 planes with the
+    same inlet (and no sponge, which acts only near the far outlet) computes
+    those planes exactly.  Every plane beyond K must still be exactly at rest.
+    """
+    cfg = channel_config(cfg_index)
+    lat = _lat(cfg)
+    lat.step(steps)
+    front_gpu = lat.get_f_planes(0, steps + 1)
+    g = lat.state_view()
+    at_rest = bool((g[:, :, :, steps + 1:] == 0).all().item())
+    sub = dict(cfg)
+    sub["nx"] = 2 * steps + 2
+    sub["sponge_cells"] = 0
+    ora = OracleChannel.from_config(sub)
+    from oracle.lattice import W
+    ratio = 0.0
+    for _ in range(steps):
+        ora.step(1)
+        ratio = max(ratio, float(np.max(np.abs(ora.f - W[:, None, None, None]) / ora.f)))
+    rel = _rel(front_gpu, ora.f[:, :, :, : steps + 1])
+    # FP16 store: K roundings of at most 2^-11 |g|/f each (see test_half_store_against_oracle)
+    tol = FP32_F_TOL if cfg["store"] == "f32" else 4.0 * np.sqrt(steps) * 2.0 ** -11 * ratio
+    print(f"[gpu] {cfg['name']} ({cfg['store']}) front after {steps} steps: max rel err {rel.max():.3e}", flush=True)
+    assert rel.max() < tol
+    assert at_rest
+    lat.close()
+
+
+@pytest.mark.parametrize("store,unit", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+def test_half_store_against_oracle(store, unit):
+    """FP16/BF16 deviation store against the FP64 oracle, with a derived bound.
+
+    Each step rounds every stored g_i to nearest (relative half-ulp `unit`),
+    moving f_i by at most unit * |g_i| / f_i.  The roundings of K steps are
+    independent, so the accumulated error stays within
+    4 sqrt(K) * unit * max_t max_i |g_i / f_i| (four standard deviations of
+    a random walk whose steps are bounded by the worst single rounding).
+    """
+    cfg = small_channel(40, 12, 8, n_modes=20, seed=2)
+    lat = _lat(cfg, store=store)
+    ora = OracleChannel.from_config(cfg)
+    from oracle.lattice import W
+    K = 20
+    ratio = 0.0
+    for _ in range(K):
+        ora.step(1)
+        ratio = max(ratio, float(np.max(np.abs(ora.f - W[:, None, None, None]) / ora.f)))
+    lat.step(K)
+    rel = _rel(lat.get_f(), ora.f)
+    bound = 4.0 * np.sqrt(K) * unit * ratio
+    print(f"[gpu] {store}: max rel err after {K} steps {rel.max():.3e}, bound {bound:.3e} (max|g/f| {ratio:.3f})",
+          flush=True)
+    assert rel.max() < bound
+    lat.close()
+
+
+def test_half_store_rounding_is_nearest_even():
+    """set_f rounds g = f - w to the nearest FP16/BF16 value (ties to even).
+
+    The import may round the FP64 deviation directly or through FP32 first;
+    both are nearest roundings, and each stored value must equal one of them.
+    """
+    from paper_2205_02774_amd import Lattice
+    from oracle.lattice import W
+    nx, ny, nz = 8, 4, 2
+    g = perturbed_state(nx, ny, nz, seed=3, amplitude=0.3)
+    f = W[:, None, None, None] + g
+    gd = f - W[:, None, None, None]
+    cands = {
+        "f16": (gd.astype(np.float16).astype(np.float64),
+                gd.astype(np.float32).astype(np.float16).astype(np.float64)),
+        "bf16": (torch.from_numpy(gd).to(torch.bfloat16).to(torch.float64).numpy(),
+                 torch.from_numpy(gd.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()),
+    }
+    for store, (single, double) in cands.items():
+        lat = Lattice(nx, ny, nz, device="cuda:0", store=store, periodic_x=True, nu_lb=1e-2)
+        lat.set_f(f)
+        back = lat.get_f() - W[:, None, None, None]
+        ok = (back == single) | (back == double)
+        print(f"[gpu] {store} import: {int((back == single).sum())} single-rounded, "
+              f"{int((back == double).sum())} via FP32, {int((~ok).sum())} other", flush=True)
+        assert ok.all()
+        lat.close()
+
+
+def test_determinism_and_checkpoint_restore():
+    cfg = channel_config(0)
+    a = _lat(cfg)
+    a.stats_reset()
+    a.step(30)
+    ck = a.checkpoint()
+    a.step(30)
+    fa, sa = a.get_f(), a.get_stats()[0]
+    b = _lat(cfg)
+    b.stats_reset()
+    b.step(60)
+    assert np.array_equal(b.get_f(), fa)
+    assert np.array_equal(b.get_stats()[0], sa)
+    c = _lat(cfg)
+    c.restore(ck)
+    assert c.get_step() == 30
+    c.step(30)
+    assert np.array_equal(c.get_f(), fa)
+    assert np.array_equal(c.get_stats()[0], sa)
+    for h in (a, b, c):
+        h.close()
+
+
+def test_error_paths():
+    from paper_2205_02774_amd import Lattice, abi
+    cfg = channel_config(0)
+    lat = Lattice(64, 32, 32, device="cuda:0", nu_lb=1e-3, max_modes=50, max_rans=32)
+    with pytest.raises(abi.StglbmError) as e:
+        lat.step(1)
+    assert e.value.code == abi.E_STATE
+    lat.close()
+    per = Lattice(16, 8, 4, device="cuda:0", periodic_x=True, nu_lb=1e-2)
+    f = per.get_f()
+    f[3, 1, 2, 5] = np.nan
+    per.set_f(f)
+    per.step(2)
+    with pytest.raises(abi.StglbmError) as e:
+        per.sync()
+    assert e.value.code == abi.E_UNSTABLE
+    with pytest.raises(abi.StglbmError) as e:
+        per.stg_generate(1)
+    assert e.value.code == abi.E_STATE
+    per.close()
+    lat = _lat(cfg)
+    bad = dict(cfg["rans"])
+    bad["y"] = bad["y"][::-1].copy()
+    with pytest.raises(abi.StglbmError) as e:
+        lat.set_rans_inlet(bad, delta=1.0, nu_phys=cfg["nu_phys"], c_x=lat.c_x, c_t=lat.c_t, U_b=bad["U_b"],
+                           n_modes=50, alpha=0.05, seed=0)
+    assert e.value.code == abi.E_INVAL
+    lat.close()
