@@ -1,0 +1,204 @@
+"""Benchmark of the STG-LBM step on one MI355X.
+
+One step = the STG inlet plane + the fused stream-collide pass over every
+cell (inlet rebuild, outlet, sponge, Smagorinsky, regularized collision,
+FP64 statistics), on the 512x128x256 Re_tau = 180 channel (600 modes, RANS
+input on a 96-cell stretched grid).  Inputs are resident in HBM; W warm-up
+steps run first, then exactly K steps are timed between two device
+synchronizations.  The FP16- and BF16-store variants of the same workload
+are timed the same way.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                       # MI355X HBM3E
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_2205_02774_amd", "csrc", "lattice_kernels.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, store):
+    """HBM bytes per step-kernel launch from committed counter runs, if the kernel is unchanged."""
+    path = os.path.join(PROFILES, f"traffic_{workload}_{store}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_variant(cfg, store, steps, warmup, stats=True):
+    import torch
+    from paper_2205_02774_amd import channel_from_config
+
+    t0 = time.perf_counter()
+    lat = channel_from_config(cfg, store=store, device="cuda:0")
+    lat.step(warmup)
+    lat.sync()
+    log(f"[bench] {cfg['name']} {store}: setup + {warmup} warm-up steps in {time.perf_counter() - t0:.1f} s")
+    if stats:
+        lat.stats_reset()
+    lat.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat.step(steps)
+    lat.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    prof = lat.profile_read()
+    lat.profile(False)
+    st, ns = lat.get_stats()
+    assert ns == (steps if stats else 0)
+    cells = cfg["cells"]
+    bytes_per_cell = 2 * 19 * (4 if store == "f32" else 2)
+    k_ms = prof["step_ms"] / prof["step_launches"]
+    out = {
+        "store": store,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "mlups": cells * steps / elapsed / 1e6,
+        "step_kernel_ms": k_ms,
+        "stg_kernel_ms": prof["stg_ms"] / max(1, prof["stg_launches"]),
+        "bytes_per_launch": bytes_per_cell * cells,
+        "achieved_gbs": bytes_per_cell * cells / (k_ms * 1e-3) / 1e9,
+        "mean_u_lb": float(st[..., 0].sum() / (ns * cells)),
+    }
+    log(f"[bench] {store}: {out['ms_per_step']:.4f} ms/step, {out['mlups']:.0f} MLUPS, step kernel "
+        f"{k_ms:.4f} ms = {out['achieved_gbs']:.0f} GB/s, STG {out['stg_kernel_ms'] * 1e3:.1f} us")
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(cfg, nz_sample, steps):
+    """Time the FP64 oracle on a spanwise slab of the same channel in a 1-thread subprocess."""
+    code = f"""
+import json, os, sys, time
+sys.path.insert(0, {ROOT!r})
+from workloads import channel_config
+from oracle import OracleChannel
+cfg = channel_config({cfg['name']!r})
+cfg['nz'] = {nz_sample}
+cfg['cells'] = cfg['nx'] * cfg['ny'] * cfg['nz']
+ch = OracleChannel.from_config(cfg)
+ch.stats_reset()
+ch.step(1)
+t0 = time.perf_counter()
+ch.step({steps})
+dt = time.perf_counter() - t0
+print(json.dumps({{"cells": cfg['cells'], "steps": {steps}, "seconds": dt}}))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=900)
+    if res.returncode != 0:
+        log(res.stderr[-2000:])
+        return None
+    rec = json.loads(res.stdout.strip().splitlines()[-1])
+    return {
+        "value": rec["cells"] * rec["steps"] / rec["seconds"] / 1e6,
+        "unit": "MLUPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{cfg['nx']}x{cfg['ny']}x{nz_sample} spanwise slab of {cfg['name']} (same inlet), "
+                  f"{steps} steps after 1 untimed, FP64 NumPy, 1 thread; {rec['seconds']:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20000)
+    ap.add_argument("--workload", default="channel-512x128x256")
+    ap.add_argument("--variants", default="f16,bf16", help="extra store types timed on the same workload")
+    ap.add_argument("--variant-warmup", type=int, default=2000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-nz", type=int, default=32)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the x-slab multi-GPU "
+              f"decomposition is a design, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    from paper_2205_02774_amd import abi
+    if not os.path.exists(abi.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    from workloads import channel_config
+
+    cfg = channel_config(args.workload)
+    main_run = run_variant(cfg, cfg["store"], args.steps, args.warmup)
+    variants = {}
+    for v in [s for s in args.variants.split(",") if s]:
+        r = run_variant(cfg, v, args.steps, args.variant_warmup)
+        variants[v] = {
+            "value": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
+            "step_kernel_ms": round(r["step_kernel_ms"], 5),
+            "roofline_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+            "speedup_vs_f32": round(r["mlups"] / main_run["mlups"], 3),
+            "warmup": args.variant_warmup,
+        }
+    traffic = measured_traffic(args.workload, cfg["store"])
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_nz, args.cpu_steps)
+    line = {
+        "metric": "MLUPS + % HBM roofline (FP32 vs FP16-store STG-LBM); p50/p99 job latency",
+        "value": round(main_run["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": cfg["name"], "lattice": [cfg["nx"], cfg["ny"], cfg["nz"]], "cells": cfg["cells"],
+            "re_tau": cfg["re_tau"], "n_modes": cfg["n_modes"], "rans_grid": cfg["rans_grid"],
+            "store": cfg["store"], "statistics": "FP64, every timed step", "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "step_kernel (fused stream-collide)",
+            "achieved": round(main_run["achieved_gbs"], 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(main_run["achieved_gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": main_run["bytes_per_launch"],
+            "step_kernel_ms": round(main_run["step_kernel_ms"], 5),
+            "stg_kernel_ms": round(main_run["stg_kernel_ms"], 5),
+        },
+        "variants": variants,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
