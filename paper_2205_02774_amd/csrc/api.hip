@@ -33,6 +33,17 @@ struct Layout {
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// The step kernel addresses the populations through raw buffer resources of
+// at most 4 GiB - 1 each: 19, 10 or 5 population planes per resource.
+int population_groups(uint64_t cells, int sbytes) {
+  const uint64_t plane = cells * static_cast<uint64_t>(sbytes);
+  const uint64_t lim = 0xffffffffull;
+  if (19 * plane <= lim) return 1;
+  if (10 * plane <= lim) return 2;
+  if (5 * plane <= lim) return 4;
+  return 0;
+}
+
 int store_bytes(int store) { return store == STGLBM_F32 ? 4 : 2; }
 
 const char* check_desc(const stglbm_lattice_desc* d) {
@@ -40,6 +51,8 @@ const char* check_desc(const stglbm_lattice_desc* d) {
   if (d->nx < 2 || d->ny < 2 || d->nz < 1) return "lattice must have nx >= 2, ny >= 2, nz >= 1";
   if (static_cast<long long>(d->nx) * d->ny * d->nz > 0x7fffffffLL) return "lattice has 2^31 cells or more";
   if (d->store < 0 || d->store > 2) return "unknown store type";
+  if (population_groups(static_cast<uint64_t>(d->nx) * d->ny * d->nz, d->store == STGLBM_F32 ? 4 : 2) == 0)
+    return "lattice too large: one population plane must stay below 858 MB";
   if (!(d->nu_lb > 0.0) || !std::isfinite(d->nu_lb)) return "nu_lb must be positive";
   if (!(d->cs_smag >= 0.0)) return "cs_smag must be >= 0";
   if (!d->periodic_x) {
@@ -184,6 +197,7 @@ StepParams step_params(stglbm_t h) {
   p.nx = d.nx; p.ny = d.ny; p.nz = d.nz;
   p.nxt = h->L.nxt; p.slots = h->L.slots; p.lw = h->L.lw; p.nblocks = h->L.nblocks;
   p.remap = (p.nblocks % 8 == 0) ? 1 : 0;
+  p.groups = population_groups(h->cells(), store_bytes(d.store));
   p.periodic_x = d.periodic_x;
   p.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
   const double tau0 = 0.5 + 3.0 * d.nu_lb;

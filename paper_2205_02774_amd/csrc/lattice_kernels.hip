@@ -114,13 +114,22 @@ __device__ __forceinline__ void regularized_rebuild(float (&g)[kQ], float drho, 
   }
 }
 
-template <class Codec, bool STATS>
+// Buffer resource word 3 for gfx9-family targets (raw, untyped dword access).
+constexpr int kBufferWord3 = 0x00020000;
+
+template <int NG>
+struct Groups {
+  static constexpr int kPer = (kQ + NG - 1) / NG;   // populations per buffer resource
+};
+
+template <class Codec, bool STATS, bool FORCE, int NG>
 __global__ __launch_bounds__(64 * kWavesZ) void step_kernel(StepParams p) {
   using S = typename Codec::storage;
-  const S* __restrict__ gin = static_cast<const S*>(p.gin);
-  S* __restrict__ gout = static_cast<S*>(p.gout);
+  constexpr int PER = Groups<NG>::kPer;
+  constexpr int SB = static_cast<int>(sizeof(S));
   const int lane = threadIdx.x;
-  const int wz = threadIdx.y;
+  // a block row of 64 threads is one wave, so threadIdx.y is uniform per wave
+  const int wz = __builtin_amdgcn_readfirstlane(threadIdx.y);
   int b = blockIdx.x;
   if (p.remap) {
     const int per = p.nblocks >> 3;
@@ -131,7 +140,24 @@ __global__ __launch_bounds__(64 * kWavesZ) void step_kernel(StepParams p) {
   const int y = rest % p.ny;
   const int slot = rest / p.ny;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
-  const long long plane = p.plane;
+  const unsigned plane_bytes = static_cast<unsigned>(p.plane) * SB;
+
+  // One raw buffer resource per group of PER populations, so each resource
+  // spans less than 4 GiB; offsets are (population in group) * plane + row
+  // start in the scalar offset and x in the per-lane offset.
+  __amdgpu_buffer_rsrc_t rin[NG], rout[NG];
+#pragma unroll
+  for (int gi = 0; gi < NG; ++gi) {
+    const int npop = (gi + 1) * PER <= kQ ? PER : kQ - gi * PER;
+    const long long off = (long long)gi * PER * p.plane;
+    rin[gi] = __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(static_cast<const S*>(p.gin)) + off, (short)0,
+                                                npop * plane_bytes, kBufferWord3);
+    rout[gi] = __builtin_amdgcn_make_buffer_rsrc(static_cast<S*>(p.gout) + off, (short)0,
+                                                 npop * plane_bytes, kBufferWord3);
+  }
+
+  // Lanes past the end of a ragged row repeat the last cell exactly (same
+  // inputs, same stores) and are left out of the statistics and flags.
   const int x = xt * 64 + lane;
   const bool active = x < nx;
   const int xc = active ? x : nx - 1;
@@ -143,8 +169,10 @@ __global__ __launch_bounds__(64 * kWavesZ) void step_kernel(StepParams p) {
     xm = xm < 0 ? 0 : xm;               // entering through the inlet: rebuilt
     xp = xp >= nx ? nx - 1 : xp;        // entering through the outlet: rebuilt
   }
-  const bool inlet = !p.periodic_x && x == 0;
-  const bool outlet = !p.periodic_x && x == nx - 1;
+  const unsigned vx[3] = {static_cast<unsigned>(xm * SB), static_cast<unsigned>(xc * SB),
+                          static_cast<unsigned>(xp * SB)};   // source x = x - c_x for c_x = +1, 0, -1
+  const bool inlet = !p.periodic_x && xc == 0;
+  const bool outlet = !p.periodic_x && xc == nx - 1;
   const float sp = p.sponge[xc];
 
   float acc[9];
@@ -158,19 +186,28 @@ __global__ __launch_bounds__(64 * kWavesZ) void step_kernel(StepParams p) {
     if (z >= nz) break;
     const int zm = z == 0 ? nz - 1 : z - 1;
     const int zp = z == nz - 1 ? 0 : z + 1;
-    const int here = (z * ny + y) * nx + xc;
+    const unsigned row_here = static_cast<unsigned>((z * ny + y) * nx) * SB;
 
     // pull streaming: g_i(x) <- g_i(x - c_i); bounce-back g_opp(i)(x) behind a wall
     float g[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
       const int ys = y - CY[i];
-      const bool wall = ys < 0 || ys >= ny;
+      const bool wall = ys < 0 || ys >= ny;            // uniform over the block
       const int zs = CZ[i] == 0 ? z : (CZ[i] > 0 ? zm : zp);
-      const int xs = CX[i] == 0 ? xc : (CX[i] > 0 ? xm : xp);
       const int pop = wall ? OPPOSITE[i] : i;
-      const int off = wall ? here : (zs * ny + ys) * nx + xs;
-      g[i] = Codec::decode(gin[pop * plane + off]);
+      const unsigned row = wall ? row_here : static_cast<unsigned>((zs * ny + ys) * nx) * SB;
+      const unsigned voff = wall ? vx[1] : vx[1 - CX[i]];
+      const unsigned soff = static_cast<unsigned>(pop % PER) * plane_bytes + row;
+      __amdgpu_buffer_rsrc_t r = rin[0];
+#pragma unroll
+      for (int gi = 1; gi < NG; ++gi)
+        if (pop / PER == gi) r = rin[gi];
+      if constexpr (SB == 4) {
+        g[i] = Codec::decode(__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0)));
+      } else {
+        g[i] = Codec::decode(__builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+      }
     }
 
     if (inlet) {
@@ -197,35 +234,52 @@ __global__ __launch_bounds__(64 * kWavesZ) void step_kernel(StepParams p) {
       regularized_rebuild<-1>(g, p.rho_out_m1, ux, 0.0f, 0.0f);
     }
 
-    // Moments as exact integer combinations of the g_i.  Each g is split into
-    // hi (g rounded to a multiple of 2^-20, so sums of hi are exact in FP32
-    // while |sum| < 16) and lo = g - hi (exact, |lo| <= 2^-21).
-    float dh = 0.f, dl = 0.f;                          // sum g
-    float jxh = 0.f, jxl = 0.f, jyh = 0.f, jyl = 0.f, jzh = 0.f, jzl = 0.f;   // sum c g
-    float hxx = 0.f, hyy = 0.f, hzz = 0.f, hxy = 0.f, hxz = 0.f, hyz = 0.f;  // sum (3 c_a c_b - d_ab) g
+    // Moments.  Each g is split into hi (rounded to a multiple of 2^-20, so
+    // integer combinations of hi are exact in FP32 while |sum| < 16) and
+    // lo = g - hi (exact).  Opposite pairs (a, a+1) give exact sums/differences.
+    float h[kQ], l[kQ];
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-      const float h = (g[i] + kSplit) - kSplit;
-      const float l = g[i] - h;
-      dh += h;
-      dl += l;
-      if (CX[i]) { jxh += CX[i] * h; jxl += CX[i] * l; }
-      if (CY[i]) { jyh += CY[i] * h; jyl += CY[i] * l; }
-      if (CZ[i]) { jzh += CZ[i] * h; jzl += CZ[i] * l; }
-      hxx += (3 * CX[i] * CX[i] - 1) * g[i];
-      hyy += (3 * CY[i] * CY[i] - 1) * g[i];
-      hzz += (3 * CZ[i] * CZ[i] - 1) * g[i];
-      if (CX[i] * CY[i]) hxy += (3 * CX[i] * CY[i]) * g[i];
-      if (CX[i] * CZ[i]) hxz += (3 * CX[i] * CZ[i]) * g[i];
-      if (CY[i] * CZ[i]) hyz += (3 * CY[i] * CZ[i]) * g[i];
+      h[i] = (g[i] + kSplit) - kSplit;
+      l[i] = g[i] - h[i];
     }
+    // pairs k = 0..8: (1,2) x, (3,4) y, (5,6) z, (7,8) xy+, (9,10) xy-, (11,12) xz+, (13,14) xz-, (15,16) yz+, (17,18) yz-
+    float sh[9], dhh[9], sl[9], dll[9], sg[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const int a = 2 * k + 1, c = 2 * k + 2;
+      sh[k] = h[a] + h[c];
+      dhh[k] = h[a] - h[c];
+      sl[k] = l[a] + l[c];
+      dll[k] = l[a] - l[c];
+      sg[k] = g[a] + g[c];
+    }
+    const float dh = h[0] + (((sh[0] + sh[1]) + (sh[2] + sh[3])) + ((sh[4] + sh[5]) + ((sh[6] + sh[7]) + sh[8])));
+    const float dl = l[0] + (((sl[0] + sl[1]) + (sl[2] + sl[3])) + ((sl[4] + sl[5]) + ((sl[6] + sl[7]) + sl[8])));
+    // sum c g as hi + lo
+    const float jxh = (dhh[0] + (dhh[3] + dhh[4])) + (dhh[5] + dhh[6]);
+    const float jyh = (dhh[1] + (dhh[3] - dhh[4])) + (dhh[7] + dhh[8]);
+    const float jzh = (dhh[2] + (dhh[5] - dhh[6])) + (dhh[7] - dhh[8]);
+    const float jxl = (dll[0] + (dll[3] + dll[4])) + (dll[5] + dll[6]);
+    const float jyl = (dll[1] + (dll[3] - dll[4])) + (dll[7] + dll[8]);
+    const float jzl = (dll[2] + (dll[5] - dll[6])) + (dll[7] - dll[8]);
     const float drho = dh + dl;
+    const float gsum = g[0] + (((sg[0] + sg[1]) + (sg[2] + sg[3])) + ((sg[4] + sg[5]) + ((sg[6] + sg[7]) + sg[8])));
+    // sum (3 c_a c_b - delta_ab) g: 3 (sum of the pairs with c_a != 0) - sum g
+    const float hxx = 3.0f * (sg[0] + ((sg[3] + sg[4]) + (sg[5] + sg[6]))) - gsum;
+    const float hyy = 3.0f * (sg[1] + ((sg[3] + sg[4]) + (sg[7] + sg[8]))) - gsum;
+    const float hzz = 3.0f * (sg[2] + ((sg[5] + sg[6]) + (sg[7] + sg[8]))) - gsum;
+    const float hxy = 3.0f * (sg[3] - sg[4]);
+    const float hxz = 3.0f * (sg[5] - sg[6]);
+    const float hyz = 3.0f * (sg[7] - sg[8]);
+
     const float rho = 1.0f + drho;
-    const float irho = 1.0f / rho;
+    float irho = __builtin_amdgcn_rcpf(rho);
+    irho = __builtin_fmaf(irho, __builtin_fmaf(-rho, irho, 1.0f), irho);   // one Newton step
     // rho u = sum c f + F/2 (eq. momentum)
-    const float ux = ((jxh + jxl) + 0.5f * p.fx) * irho;
-    const float uy = ((jyh + jyl) + 0.5f * p.fy) * irho;
-    const float uz = ((jzh + jzl) + 0.5f * p.fz) * irho;
+    const float ux = ((jxh + jxl) + (FORCE ? 0.5f * p.fx : 0.0f)) * irho;
+    const float uy = ((jyh + jyl) + (FORCE ? 0.5f * p.fy : 0.0f)) * irho;
+    const float uz = ((jzh + jzl) + (FORCE ? 0.5f * p.fz : 0.0f)) * irho;
     bad |= !(fabsf(drho) < 0.5f);
 
     // Pi_neq = sum c c (f - f_eq) = sum (c c - c_s^2 I) g - rho u u
@@ -237,36 +291,59 @@ __global__ __launch_bounds__(64 * kWavesZ) void step_kernel(StepParams p) {
     const float nyz = hyz * (1.0f / 3.0f) - rho * uy * uz;
     const float q2 = nxx * nxx + nyy * nyy + nzz * nzz + 2.0f * (nxy * nxy + nxz * nxz + nyz * nyz);
     // tau_eff - 1/2 = (tau0 - 1/2) + X / (2 (sqrt(tau0^2 + X) + tau0)), X = 18 sqrt2 Cs^2 Q^1/2 / rho
-    const float X = p.c18 * sqrtf(q2) * irho;
-    const float s = (p.s0 + X / (2.0f * (sqrtf(p.tau0_sq + X) + p.tau0))) * sp;
-    const float itau = 1.0f / (0.5f + s);
+    const float X = p.c18 * __builtin_amdgcn_sqrtf(q2) * irho;
+    const float s = (p.s0 + X * __builtin_amdgcn_rcpf(2.0f * (__builtin_amdgcn_sqrtf(p.tau0_sq + X) + p.tau0))) * sp;
+    const float itau = __builtin_amdgcn_rcpf(0.5f + s);
     const float omw = (s - 0.5f) * itau;      // 1 - 1/tau
-    const float omhw = s * itau;              // 1 - 1/(2 tau)
+    const float omw45 = 4.5f * omw;
     const float tr3 = (nxx + nyy + nzz) * (1.0f / 3.0f);
     const float uu15 = 1.5f * (ux * ux + uy * uy + uz * uz);
-    const float uF = ux * p.fx + uy * p.fy + uz * p.fz;
 
-    // g_i' = w_i [drho + 3 c_i.(rho u) + rho (4.5 (c_i.u)^2 - 1.5 u.u)
-    //             + (1 - 1/tau) (4.5 Q_i:Pi_neq - 1.5 c_i.F) + Guo source]
-    // with drho + 3 c_i.J summed exactly from the hi parts; w_i applied as
-    // w_hi S + w_lo S so the rounding of w_i leaves no systematic bias.
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-      const float qp = (CX[i] * CX[i]) * nxx + (CY[i] * CY[i]) * nyy + (CZ[i] * CZ[i]) * nzz +
-                       2.0f * ((CX[i] * CY[i]) * nxy + (CX[i] * CZ[i]) * nxz + (CY[i] * CZ[i]) * nyz) - tr3;
-      const float ah = dh + 3.0f * (CX[i] * jxh + CY[i] * jyh + CZ[i] * jzh);   // exact
-      const float al = dl + 3.0f * (CX[i] * jxl + CY[i] * jyl + CZ[i] * jzl);
-      float rest = rho * (4.5f * cu * cu - uu15) + omw * (4.5f * qp);
-      if (p.has_force) {
-        const float cF = CX[i] * p.fx + CY[i] * p.fy + CZ[i] * p.fz;
-        // 3 c.(F/2) from rho u, the relaxed first-order part -F/2, and Guo's source
-        rest += 1.5f * cF + omw * (-1.5f * cF) + omhw * (3.0f * (cF - uF) + 9.0f * cu * cF);
-      }
-      const float S = ah + (al + rest);
-      const float out = wmul(i, S);
-      if (active) __builtin_nontemporal_store(Codec::encode(out), &gout[i * plane + here]);
+    // Output.  For a pair (a, opp(a)) with velocity c:
+    //   g'/w = [drho + 3 c.J] + rho (4.5 (c.u)^2 - 1.5 u.u) + (1 - 1/tau) 4.5 Q:Pi_neq (+ force terms)
+    // the bracket is exact from the hi parts (big, odd in c); everything else is
+    // small and split into an even part E and an odd part O.  w_i is applied as
+    // w_hi S + w_lo S (one rounding, no systematic bias from rounding w_i).
+    const float omhw = FORCE ? s * itau : 0.0f;         // 1 - 1/(2 tau)
+    const float uF = FORCE ? ux * p.fx + uy * p.fy + uz * p.fz : 0.0f;
+    const float base_e = dl - rho * uu15;
+    const unsigned voff_here = vx[1];
+#define STGLBM_STORE(I, VAL)                                                                              \
+    do {                                                                                                  \
+      const float v_ = (VAL);                                                                             \
+      __amdgpu_buffer_rsrc_t r_ = rout[0];                                                                \
+      _Pragma("unroll") for (int gi = 1; gi < NG; ++gi) if ((I) / PER == gi) r_ = rout[gi];               \
+      const unsigned so_ = static_cast<unsigned>((I) % PER) * plane_bytes + row_here;                    \
+      if constexpr (SB == 4)                                                                              \
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, Codec::encode(v_)), r_, voff_here, so_, 2); \
+      else                                                                                                \
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, Codec::encode(v_)), r_, voff_here, so_, 2); \
+    } while (0)
+    {
+      // rest population: c = 0
+      float e0 = base_e + omw45 * (-tr3);
+      if (FORCE) e0 += -3.0f * omhw * uF;
+      STGLBM_STORE(0, wmul(0, dh + e0));
     }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const int a = 2 * k + 1;
+      const int cx = CX[a], cy = CY[a], cz = CZ[a];
+      const float cu = cx * ux + cy * uy + cz * uz;
+      const float qp = (cx * cx) * nxx + (cy * cy) * nyy + (cz * cz) * nzz +
+                       2.0f * ((cx * cy) * nxy + (cx * cz) * nxz + (cy * cz) * nyz) - tr3;
+      float E = __builtin_fmaf(rho * 4.5f * cu, cu, base_e) + omw45 * qp;
+      const float Oh = 3.0f * (cx * jxh + cy * jyh + cz * jzh);     // exact
+      float Ol = 3.0f * (cx * jxl + cy * jyl + cz * jzl);
+      if (FORCE) {
+        const float cF = cx * p.fx + cy * p.fy + cz * p.fz;
+        E += omhw * (9.0f * cu * cF - 3.0f * uF);
+        Ol += cF * (1.5f * (1.0f - omw) + 3.0f * omhw);
+      }
+      STGLBM_STORE(a, wmul(a, (dh + Oh) + (E + Ol)));
+      STGLBM_STORE(a + 1, wmul(a + 1, (dh - Oh) + (E - Ol)));
+    }
+#undef STGLBM_STORE
 
     if (STATS) {
       acc[0] += ux;
@@ -378,28 +455,39 @@ int grid_for(unsigned long long n, int block) {
   return static_cast<int>(b);
 }
 
+template <class Codec, int NG>
+hipError_t launch_step_ng(const StepParams& p, bool stats, hipStream_t s) {
+  const dim3 block(64, kWavesZ);
+  const dim3 grid(p.nblocks);
+  if (p.has_force) {
+    if (stats) step_kernel<Codec, true, true, NG><<<grid, block, 0, s>>>(p);
+    else step_kernel<Codec, false, true, NG><<<grid, block, 0, s>>>(p);
+  } else {
+    if (stats) step_kernel<Codec, true, false, NG><<<grid, block, 0, s>>>(p);
+    else step_kernel<Codec, false, false, NG><<<grid, block, 0, s>>>(p);
+  }
+  return hipGetLastError();
+}
+
+template <class Codec>
+hipError_t launch_step_codec(const StepParams& p, bool stats, hipStream_t s) {
+  switch (p.groups) {
+    case 1: return launch_step_ng<Codec, 1>(p, stats, s);
+    case 2: return launch_step_ng<Codec, 2>(p, stats, s);
+    case 4: return launch_step_ng<Codec, 4>(p, stats, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_step(const StepParams& p, int store, bool stats, hipStream_t s) {
-  const dim3 block(64, kWavesZ);
-  const dim3 grid(p.nblocks);
   switch (store) {
-    case 0:
-      if (stats) step_kernel<CodecF32, true><<<grid, block, 0, s>>>(p);
-      else step_kernel<CodecF32, false><<<grid, block, 0, s>>>(p);
-      break;
-    case 1:
-      if (stats) step_kernel<CodecF16, true><<<grid, block, 0, s>>>(p);
-      else step_kernel<CodecF16, false><<<grid, block, 0, s>>>(p);
-      break;
-    case 2:
-      if (stats) step_kernel<CodecBF16, true><<<grid, block, 0, s>>>(p);
-      else step_kernel<CodecBF16, false><<<grid, block, 0, s>>>(p);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case 0: return launch_step_codec<CodecF32>(p, stats, s);
+    case 1: return launch_step_codec<CodecF16>(p, stats, s);
+    case 2: return launch_step_codec<CodecBF16>(p, stats, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(void* ptr, unsigned long long bytes, hipStream_t s) {

@@ -31,6 +31,7 @@ struct StepParams {
   int remap;                // XCD-aware tile order (nblocks % 8 == 0)
   int periodic_x;
   int has_force;
+  int groups;               // buffer resources the populations are split over (1, 2 or 4)
   float tau0, tau0_sq;      // tau0 and tau0^2 (rounded from FP64)
   float s0;                 // tau0 - 1/2 (rounded from FP64)
   float c18;                // 18 sqrt(2) Cs^2
