@@ -8,7 +8,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libstglbm.so")
+LIB_PATH = os.environ.get("STGLBM_LIB") or os.path.join(HERE, "libstglbm.so")
 
 OK = 0
 E_INVAL = -1

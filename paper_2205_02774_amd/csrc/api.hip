@@ -28,7 +28,7 @@ thread_local std::string g_lib_error;
 struct Layout {
   uint64_t g[2] = {0, 0}, stats = 0, sponge = 0, flag = 0, ubc = 0, rans = 0, rows = 0, modes = 0,
            sqrtq = 0, bz = 0, sig = 0, scalars = 0, total = 0;
-  int nxt = 0, slots = 0, lw = 0, nblocks = 0;
+  int nxt = 0, wx = 1, wz = 1, nxg = 0, slots = 0, lw = 0, nblocks = 0;
 };
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -69,18 +69,31 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   Layout L;
   const uint64_t cells = static_cast<uint64_t>(d->nx) * d->ny * d->nz;
   L.nxt = (d->nx + 63) / 64;
-  const int base = L.nxt * d->ny;
-  const int zmax = (d->nz + kWavesZ - 1) / kWavesZ;
-  int slots = (2048 + base - 1) / base;            // aim for >= 2048 blocks
-  if (slots < 1) slots = 1;
-  if (slots > zmax) slots = zmax;
-  int lw = (d->nz + kWavesZ * slots - 1) / (kWavesZ * slots);
-  if (const char* env = std::getenv("STGLBM_LW")) {
-    const int v = std::atoi(env);
-    if (v >= 1) lw = v;
+  // Block shape: wx waves along x (consecutive 64-cell tiles of one row) times
+  // wz waves along z, each wave stepping lw cells in z.  Default: whole rows
+  // of up to 512 cells per block, one wave deep, lw chosen for >= 2048 blocks.
+  int wx = L.nxt < 8 ? L.nxt : 8;
+  int wz = 1;
+  int lw = 0;
+  if (const char* env = std::getenv("STGLBM_SHAPE")) {   // "wx,wz,lw" tuning override
+    int a = 0, b = 0, c = 0;
+    if (std::sscanf(env, "%d,%d,%d", &a, &b, &c) == 3 && a >= 1 && b >= 1 && a * b <= kMaxWavesPerBlock && c >= 0) {
+      wx = a; wz = b; lw = c;
+    }
+  }
+  L.wx = wx;
+  L.wz = wz;
+  L.nxg = (L.nxt + wx - 1) / wx;
+  const int base = L.nxg * d->ny;
+  if (lw == 0) {
+    const int zmax = (d->nz + wz - 1) / wz;
+    int slots = (2048 + base - 1) / base;
+    if (slots < 1) slots = 1;
+    if (slots > zmax) slots = zmax;
+    lw = (d->nz + wz * slots - 1) / (wz * slots);
   }
   L.lw = lw;
-  L.slots = (d->nz + kWavesZ * lw - 1) / (kWavesZ * lw);
+  L.slots = (d->nz + wz * lw - 1) / (wz * lw);
   L.nblocks = base * L.slots;
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
@@ -195,7 +208,8 @@ StepParams step_params(stglbm_t h) {
   p.gout = h->gbuf(1 - h->cur);
   p.plane = static_cast<long long>(h->cells());
   p.nx = d.nx; p.ny = d.ny; p.nz = d.nz;
-  p.nxt = h->L.nxt; p.slots = h->L.slots; p.lw = h->L.lw; p.nblocks = h->L.nblocks;
+  p.nxt = h->L.nxt; p.wx = h->L.wx; p.wz = h->L.wz; p.nxg = h->L.nxg;
+  p.slots = h->L.slots; p.lw = h->L.lw; p.nblocks = h->L.nblocks;
   p.remap = (p.nblocks % 8 == 0) ? 1 : 0;
   p.groups = population_groups(h->cells(), store_bytes(d.store));
   p.periodic_x = d.periodic_x;

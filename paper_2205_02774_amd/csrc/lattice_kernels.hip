@@ -123,22 +123,25 @@ struct Groups {
 };
 
 template <class Codec, bool STATS, bool FORCE, int NG>
-__global__ __launch_bounds__(64 * kWavesZ) void step_kernel(StepParams p) {
+__global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams p) {
   using S = typename Codec::storage;
   constexpr int PER = Groups<NG>::kPer;
   constexpr int SB = static_cast<int>(sizeof(S));
-  const int lane = threadIdx.x;
-  // a block row of 64 threads is one wave, so threadIdx.y is uniform per wave
+  const int lane = threadIdx.x & 63;
+  // every 64 consecutive threadIdx.x form one wave: wave indices are uniform
+  const int wxi = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wz = __builtin_amdgcn_readfirstlane(threadIdx.y);
   int b = blockIdx.x;
   if (p.remap) {
     const int per = p.nblocks >> 3;
     b = (b & 7) * per + (b >> 3);
   }
-  const int xt = b % p.nxt;
-  const int rest = b / p.nxt;
+  const int xg = b % p.nxg;
+  const int rest = b / p.nxg;
   const int y = rest % p.ny;
   const int slot = rest / p.ny;
+  const int xt = xg * p.wx + wxi;
+  const bool wave_live = xt < p.nxt;        // waves past the last x tile only join the reduction
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const unsigned plane_bytes = static_cast<unsigned>(p.plane) * SB;
 
@@ -180,9 +183,9 @@ __global__ __launch_bounds__(64 * kWavesZ) void step_kernel(StepParams p) {
   for (int k = 0; k < 9; ++k) acc[k] = 0.0f;
   int bad = 0;
 
-  const int z0 = slot * kWavesZ * p.lw + wz;
-  for (int it = 0; it < p.lw; ++it) {
-    const int z = z0 + it * kWavesZ;
+  const int z0 = slot * p.wz * p.lw + wz;
+  for (int it = 0; it < (wave_live ? p.lw : 0); ++it) {
+    const int z = z0 + it * p.wz;
     if (z >= nz) break;
     const int zm = z == 0 ? nz - 1 : z - 1;
     const int zp = z == nz - 1 ? 0 : z + 1;
@@ -359,24 +362,27 @@ __global__ __launch_bounds__(64 * kWavesZ) void step_kernel(StepParams p) {
   }
 
   // one flag write per wave
-  if (__any(bad && active)) {
+  if (__any(bad && active && wave_live)) {
     if (lane == 0) atomicOr(p.flag, kFlagDensity);
   }
 
   if (STATS) {
-    __shared__ float red[kWavesZ][9][64];
+    // per-(x, y) sums over the block's z range: registers, then the wz waves in LDS
+    extern __shared__ float red[];             // [wz][9][64 wx]
+    const int tx = threadIdx.x, bx = 64 * p.wx;
+    if (p.wz > 1) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) red[wz][k][lane] = acc[k];
-    __syncthreads();
-    if (wz == 0 && active) {
+      for (int k = 0; k < 9; ++k) red[(wz * 9 + k) * bx + tx] = acc[k];
+      __syncthreads();
+    }
+    if (wz == 0 && active && wave_live) {
       const long long bin = (long long)y * nx + x;
       const long long sstride = (long long)ny * nx;
       double* st = p.stats + (long long)slot * 9 * sstride + bin;
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        float v = red[0][k][lane];
-#pragma unroll
-        for (int w = 1; w < kWavesZ; ++w) v += red[w][k][lane];
+        float v = acc[k];
+        for (int w = 1; w < p.wz; ++w) v += red[(w * 9 + k) * bx + tx];
         st[k * sstride] += static_cast<double>(v);
       }
     }
@@ -457,13 +463,15 @@ int grid_for(unsigned long long n, int block) {
 
 template <class Codec, int NG>
 hipError_t launch_step_ng(const StepParams& p, bool stats, hipStream_t s) {
-  const dim3 block(64, kWavesZ);
+  if (p.wx < 1 || p.wz < 1 || p.wx * p.wz > kMaxWavesPerBlock) return hipErrorInvalidValue;
+  const dim3 block(64 * p.wx, p.wz);
   const dim3 grid(p.nblocks);
+  const size_t lds = (stats && p.wz > 1) ? sizeof(float) * 9 * 64 * p.wx * p.wz : 0;
   if (p.has_force) {
-    if (stats) step_kernel<Codec, true, true, NG><<<grid, block, 0, s>>>(p);
+    if (stats) step_kernel<Codec, true, true, NG><<<grid, block, lds, s>>>(p);
     else step_kernel<Codec, false, true, NG><<<grid, block, 0, s>>>(p);
   } else {
-    if (stats) step_kernel<Codec, true, false, NG><<<grid, block, 0, s>>>(p);
+    if (stats) step_kernel<Codec, true, false, NG><<<grid, block, lds, s>>>(p);
     else step_kernel<Codec, false, false, NG><<<grid, block, 0, s>>>(p);
   }
   return hipGetLastError();

@@ -10,7 +10,7 @@ constexpr int kQ = 19;
 constexpr int kRowFields = 18;      // U(3) k omega R(6) a(6) l_e
 constexpr int kModeFields = 8;      // k, d(3), sigma(3), phi
 constexpr int kScalars = 8;         // L_e k_min k_max alpha k_cut clamps U_b N
-constexpr int kWavesZ = 4;          // waves per block of the step kernel (spanwise)
+constexpr int kMaxWavesPerBlock = 8; // step kernel: waves along x times waves along z
 constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel
 constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
 
@@ -25,7 +25,9 @@ struct StepParams {
   long long plane;          // NX*NY*NZ
   int nx, ny, nz;
   int nxt;                  // number of 64-wide x tiles
-  int slots;                // spanwise blocks per (x tile, y); statistics slots
+  int wx, wz;               // block = wx waves along x times wz waves along z
+  int nxg;                  // x-tile groups per row: ceil(nxt / wx)
+  int slots;                // spanwise blocks per (x group, y); statistics slots
   int lw;                   // spanwise cells per wave
   int nblocks;
   int remap;                // XCD-aware tile order (nblocks % 8 == 0)
