@@ -89,6 +89,23 @@ def run_variant(cfg, store, steps, warmup, stats=True):
     return out
 
 
+def serving_mix(scale, budget_gib, max_active, chunk):
+    """The 64-job serving mix with step budgets scaled by `scale` (Poisson arrivals, 2/s)."""
+    from paper_2205_02774_amd.serve import Server, DeviceExecutor
+    from workloads import serving_jobs, job_config
+    jobs = []
+    for spec in serving_jobs(64, seed=4):
+        steps = max(1, int(round(spec["steps"] * scale)))
+        jobs.append({"id": spec["id"], "arrival_s": spec["arrival_s"], "steps": steps, "cfg": job_config(spec)})
+    srv = Server(int(budget_gib * 2 ** 30), max_active=max_active, chunk_steps=chunk,
+                 executor=DeviceExecutor("cuda:0"))
+    res, summ = srv.run(jobs)
+    summ.update({"step_scale": scale, "budget_gib": budget_gib, "max_active": max_active, "chunk_steps": chunk,
+                 "peak_active": srv.peak_active, "peak_gib": round(srv.peak_bytes / 2 ** 30, 2)})
+    log(f"[bench] serving: {summ}")
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
+
+
 def cpu_baseline(cfg, nz_sample, steps):
     """Time the FP64 oracle on a spanwise slab of the same channel in a 1-thread subprocess."""
     code = f"""
@@ -132,6 +149,11 @@ def main():
     ap.add_argument("--variants", default="f16,bf16", help="extra store types timed on the same workload")
     ap.add_argument("--variant-warmup", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-scale", type=float, default=0.05,
+                    help="step budgets of the 64-job serving mix are scaled by this (1.0 = full mix; 0 = skip)")
+    ap.add_argument("--serve-budget-gib", type=float, default=24.0)
+    ap.add_argument("--serve-max-active", type=int, default=16)
+    ap.add_argument("--serve-chunk", type=int, default=250)
     ap.add_argument("--cpu-nz", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=4)
     args = ap.parse_args()
@@ -162,6 +184,9 @@ def main():
             "speedup_vs_f32": round(r["mlups"] / main_run["mlups"], 3),
             "warmup": args.variant_warmup,
         }
+    serving = None
+    if args.serve_scale > 0:
+        serving = serving_mix(args.serve_scale, args.serve_budget_gib, args.serve_max_active, args.serve_chunk)
     traffic = measured_traffic(args.workload, cfg["store"])
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_nz, args.cpu_steps)
     line = {
@@ -195,6 +220,7 @@ def main():
             "stg_kernel_ms": round(main_run["stg_kernel_ms"], 5),
         },
         "variants": variants,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

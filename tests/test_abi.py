@@ -68,7 +68,7 @@ def test_descriptor_validation_and_footprint(lib):
     d = make_desc(512, 128, 256, nu_lb=1.1458e-3, max_modes=600, max_rans=96)
     fp = footprint(d)
     assert fp >= 2 * 19 * 512 * 128 * 256 * 4
-    assert fp < 2 * 19 * 512 * 128 * 256 * 4 * 1.02
+    assert fp < 2 * 19 * 512 * 128 * 256 * 4 * 1.05   # + FP64 statistics slots and tables
     d16 = make_desc(512, 128, 256, nu_lb=1.1458e-3, store="f16", max_modes=600, max_rans=96)
     assert footprint(d16) < 0.52 * fp
     bad = make_desc(1, 128, 256, nu_lb=1e-3, max_modes=10, max_rans=10)

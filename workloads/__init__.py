@@ -20,7 +20,7 @@ from .rans import (
     channel_rans_profile,
     bulk_velocity_fv,
 )
-from .configs import channel_config, CONFIG_NAMES, perturbed_state, serving_jobs
+from .configs import channel_config, CONFIG_NAMES, perturbed_state, serving_jobs, job_config, small_channel
 
 __all__ = [
     "KAPPA",
@@ -35,4 +35,6 @@ __all__ = [
     "CONFIG_NAMES",
     "perturbed_state",
     "serving_jobs",
+    "job_config",
+    "small_channel",
 ]

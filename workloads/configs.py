@@ -106,6 +106,15 @@ def perturbed_state(nx, ny, nz, seed, amplitude=1e-3):
 LADDER = ((64, 32, 32), (128, 64, 64), (256, 64, 128), (512, 128, 256))
 
 
+def job_config(job):
+    """Channel configuration of a serving job (RANS input evaluated at its lattice rows)."""
+    cfg = small_channel(job["nx"], job["ny"], job["nz"], re_tau=job["re_tau"], n_modes=job["n_modes"],
+                        alpha=job.get("alpha", 0.0), seed=job["seed"], store=job["store"])
+    if "u_b_lb" in job:
+        cfg["u_b_lb"] = job["u_b_lb"]
+    return cfg
+
+
 def serving_jobs(n_jobs=64, seed=4, rate_per_s=2.0, ladder=LADDER,
                  steps_range=(1000, 20000), modes_range=(50, 600)):
     """Seeded serving mix: Poisson arrivals and per-job channel parameters."""
