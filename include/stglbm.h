@@ -22,7 +22,9 @@
  * Distributions.  Stored as deviations g_i = f_i - w_i in two buffers
  * (read one, write the other, swapped every step), as FP32, FP16 or BF16
  * (round to nearest even); arithmetic is FP32, statistics FP64.
- * Layout [19][NZ][NY][NX], x fastest; population order: rest;
+ * Device layout [NZ][19][NY][NX] (each z slice holds all 19 populations,
+ * x fastest); the host-side arrays of get_f/set_f/get_f_planes are
+ * [19][NZ][NY][NX].  Population order: rest;
  * +x, -x, +y, -y, +z, -z; (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0),
  * (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1),
  * (0,-1,1).
@@ -161,7 +163,8 @@ int stglbm_get_f(stglbm_t h, double* h_out, uint64_t n);
  * synchronizes. n = 19*NZ*NY*(x1-x0). */
 int stglbm_get_f_planes(stglbm_t h, int32_t x0, int32_t x1, double* h_out, uint64_t n);
 /* Device address and size in bytes of the current distributions g (store
- * type, [19][NZ][NY][NX]); valid until the next step or restore. */
+ * type, device layout [NZ][19][NY][NX]); valid until the next step or
+ * restore. */
 int stglbm_state_view(stglbm_t h, void** d_g, uint64_t* bytes);
 /* Replace the distributions by f (rounded to the store type). Synchronizes. */
 int stglbm_set_f(stglbm_t h, const double* h_in, uint64_t n);

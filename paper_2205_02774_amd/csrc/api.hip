@@ -21,38 +21,32 @@ namespace {
 constexpr int kVersion = 10000;        // 1.0.0
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kCkptMagic = 0x5354474cu;   // "STGL"
-constexpr uint32_t kCkptVersion = 1;
+constexpr uint32_t kCkptVersion = 2;   // 2: store order [NZ][19][NY][NX]
 
 thread_local std::string g_lib_error;
 
 struct Layout {
   uint64_t g[2] = {0, 0}, stats = 0, sponge = 0, flag = 0, ubc = 0, rans = 0, rows = 0, modes = 0,
            sqrtq = 0, bz = 0, sig = 0, scalars = 0, total = 0;
-  int nxt = 0, wx = 1, wz = 1, nxg = 0, slots = 0, lw = 0, nblocks = 0;
+  int vec = 1, nxt = 0, wx = 1, wz = 1, nxg = 0, slots = 0, lw = 0, zstep = 1, nblocks = 0;
 };
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// The step kernel addresses the populations through raw buffer resources of
-// at most 4 GiB - 1 each: 19, 10 or 5 population planes per resource.
-int population_groups(uint64_t cells, int sbytes) {
-  const uint64_t plane = cells * static_cast<uint64_t>(sbytes);
-  const uint64_t lim = 0xffffffffull;
-  if (19 * plane <= lim) return 1;
-  if (10 * plane <= lim) return 2;
-  if (5 * plane <= lim) return 4;
-  return 0;
-}
-
 int store_bytes(int store) { return store == STGLBM_F32 ? 4 : 2; }
+
+// The step kernel addresses one z slice of the store ([19][NY][NX] values)
+// through a raw buffer resource of at most 4 GiB - 1.
+bool slice_fits(const stglbm_lattice_desc* d) {
+  return static_cast<uint64_t>(kQ) * d->nx * d->ny * store_bytes(d->store) <= 0xffffffffull;
+}
 
 const char* check_desc(const stglbm_lattice_desc* d) {
   if (!d) return "null descriptor";
   if (d->nx < 2 || d->ny < 2 || d->nz < 1) return "lattice must have nx >= 2, ny >= 2, nz >= 1";
   if (static_cast<long long>(d->nx) * d->ny * d->nz > 0x7fffffffLL) return "lattice has 2^31 cells or more";
   if (d->store < 0 || d->store > 2) return "unknown store type";
-  if (population_groups(static_cast<uint64_t>(d->nx) * d->ny * d->nz, d->store == STGLBM_F32 ? 4 : 2) == 0)
-    return "lattice too large: one population plane must stay below 858 MB";
+  if (!slice_fits(d)) return "lattice too large: one z slice (19 NY NX values) must stay below 4 GiB";
   if (!(d->nu_lb > 0.0) || !std::isfinite(d->nu_lb)) return "nu_lb must be positive";
   if (!(d->cs_smag >= 0.0)) return "cs_smag must be >= 0";
   if (!d->periodic_x) {
@@ -68,19 +62,30 @@ const char* check_desc(const stglbm_lattice_desc* d) {
 Layout make_layout(const stglbm_lattice_desc* d) {
   Layout L;
   const uint64_t cells = static_cast<uint64_t>(d->nx) * d->ny * d->nz;
-  L.nxt = (d->nx + 63) / 64;
-  // Block shape: wx waves along x (consecutive 64-cell tiles of one row) times
-  // wz waves along z, each wave stepping lw cells in z.  Default: whole rows
-  // of up to 512 cells per block, one wave deep, lw chosen for >= 2048 blocks.
-  int wx = L.nxt < 8 ? L.nxt : 8;
+  // Each lane owns vec consecutive x cells (1, 2 or 4).  Wider lanes make
+  // 8-byte accesses but need more registers, and on MI355X one cell per lane
+  // streams fastest at the channel sizes measured, so 1 is the default.
+  int vec = 1;
+  // Block shape: wx waves along x (consecutive tiles of 64 vec cells of one
+  // row) times wz waves along z, each wave stepping lw cells in z.  Default:
+  // whole rows of up to 512 vec cells per block, one wave deep, lw chosen for
+  // >= 2048 blocks.
+  int wx = 0;
   int wz = 1;
   int lw = 0;
-  if (const char* env = std::getenv("STGLBM_SHAPE")) {   // "wx,wz,lw" tuning override
-    int a = 0, b = 0, c = 0;
-    if (std::sscanf(env, "%d,%d,%d", &a, &b, &c) == 3 && a >= 1 && b >= 1 && a * b <= kMaxWavesPerBlock && c >= 0) {
+  int interleave = 1;
+  if (const char* env = std::getenv("STGLBM_SHAPE")) {   // "wx,wz,lw[,vec[,interleave]]" tuning override
+    int a = 0, b = 0, c = 0, v = 0, il = 1;
+    const int n = std::sscanf(env, "%d,%d,%d,%d,%d", &a, &b, &c, &v, &il);
+    if (n >= 3 && a >= 1 && b >= 1 && a * b <= kMaxWavesPerBlock && c >= 0) {
       wx = a; wz = b; lw = c;
+      if (n >= 4 && (v == 1 || v == 2 || v == 4) && d->nx % v == 0) vec = v;
+      if (n >= 5) interleave = il ? 1 : 0;
     }
   }
+  L.vec = vec;
+  L.nxt = (d->nx + 64 * vec - 1) / (64 * vec);
+  if (wx == 0) wx = L.nxt < 8 ? L.nxt : 8;
   L.wx = wx;
   L.wz = wz;
   L.nxg = (L.nxt + wx - 1) / wx;
@@ -94,6 +99,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   }
   L.lw = lw;
   L.slots = (d->nz + wz * lw - 1) / (wz * lw);
+  L.zstep = interleave ? L.slots * wz : wz;
   L.nblocks = base * L.slots;
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
@@ -206,12 +212,12 @@ StepParams step_params(stglbm_t h) {
   const stglbm_lattice_desc& d = h->d;
   p.gin = h->gbuf(h->cur);
   p.gout = h->gbuf(1 - h->cur);
-  p.plane = static_cast<long long>(h->cells());
+  p.plane2d = static_cast<long long>(d.nx) * d.ny;
   p.nx = d.nx; p.ny = d.ny; p.nz = d.nz;
+  p.vec = h->L.vec;
   p.nxt = h->L.nxt; p.wx = h->L.wx; p.wz = h->L.wz; p.nxg = h->L.nxg;
-  p.slots = h->L.slots; p.lw = h->L.lw; p.nblocks = h->L.nblocks;
+  p.slots = h->L.slots; p.lw = h->L.lw; p.zstep = h->L.zstep; p.nblocks = h->L.nblocks;
   p.remap = (p.nblocks % 8 == 0) ? 1 : 0;
-  p.groups = population_groups(h->cells(), store_bytes(d.store));
   p.periodic_x = d.periodic_x;
   p.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
   const double tau0 = 0.5 + 3.0 * d.nu_lb;
@@ -466,7 +472,8 @@ int stglbm_get_f(stglbm_t h, double* h_out, uint64_t n) {
   const uint64_t chunk = h->gbytes() / sizeof(double);
   for (uint64_t off = 0; off < total; off += chunk) {
     const uint64_t cnt = std::min<uint64_t>(chunk, total - off);
-    HIP_CHECK(h, launch_export_f(h->gbuf(h->cur), h->d.store, off, cnt, h->cells(), stage, h->stream), "export kernel");
+    HIP_CHECK(h, launch_export_f(h->gbuf(h->cur), h->d.store, off, cnt, h->d.nz,
+                                 static_cast<long long>(h->d.nx) * h->d.ny, stage, h->stream), "export kernel");
     HIP_CHECK(h, hipMemcpyAsync(h_out + off, stage, cnt * sizeof(double), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync f");
     HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   }
@@ -506,7 +513,8 @@ int stglbm_set_f(stglbm_t h, const double* h_in, uint64_t n) {
   for (uint64_t off = 0; off < total; off += chunk) {
     const uint64_t cnt = std::min<uint64_t>(chunk, total - off);
     HIP_CHECK(h, hipMemcpyAsync(stage, h_in + off, cnt * sizeof(double), hipMemcpyHostToDevice, h->stream), "hipMemcpyAsync f");
-    HIP_CHECK(h, launch_import_f(stage, h->d.store, off, cnt, h->cells(), h->gbuf(h->cur), h->stream), "import kernel");
+    HIP_CHECK(h, launch_import_f(stage, h->d.store, off, cnt, h->d.nz,
+                                 static_cast<long long>(h->d.nx) * h->d.ny, h->gbuf(h->cur), h->stream), "import kernel");
     HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   }
   HIP_CHECK(h, launch_fill_zero(h->at<char>(h->L.flag), kAlign, h->stream), "flag reset");

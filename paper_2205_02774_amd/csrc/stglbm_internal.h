@@ -20,20 +20,21 @@ constexpr int kFlagInletMach = 2;   // |u_bc,x| >= 0.3 c_s at an inlet node
 
 // Fused stream-collide pass, one launch per time step.
 struct StepParams {
-  const void* gin;          // g at step n, [19][NZ][NY][NX] in the store type
+  const void* gin;          // g at step n, [NZ][19][NY][NX] in the store type
   void* gout;               // g at step n+1
-  long long plane;          // NX*NY*NZ
+  long long plane2d;        // NX*NY: one population of one z slice
   int nx, ny, nz;
-  int nxt;                  // number of 64-wide x tiles
+  int vec;                  // consecutive x cells per lane (1, 2 or 4)
+  int nxt;                  // number of x tiles of 64 * vec cells
   int wx, wz;               // block = wx waves along x times wz waves along z
   int nxg;                  // x-tile groups per row: ceil(nxt / wx)
   int slots;                // spanwise blocks per (x group, y); statistics slots
   int lw;                   // spanwise cells per wave
+  int zstep;                // z distance between a wave's rows: slots * wz (interleaved) or wz (chunked)
   int nblocks;
   int remap;                // XCD-aware tile order (nblocks % 8 == 0)
   int periodic_x;
   int has_force;
-  int groups;               // buffer resources the populations are split over (1, 2 or 4)
   float tau0, tau0_sq;      // tau0 and tau0^2 (rounded from FP64)
   float s0;                 // tau0 - 1/2 (rounded from FP64)
   float c18;                // 18 sqrt(2) Cs^2
@@ -82,12 +83,13 @@ hipError_t launch_stg(const StgParams& p, hipStream_t s);
 hipError_t launch_inlet_setup(const SetupParams& p, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, unsigned long long bytes, hipStream_t s);
 hipError_t launch_sponge(float* sponge, int nx, int cells, double K, double p, hipStream_t s);
-hipError_t launch_export_f(const void* g, int store, long long offset, long long count,
-                           long long plane, double* out, hipStream_t s);
+// Public order [19][NZ][NY][NX] <-> stored order [NZ][19][NY][NX].
+hipError_t launch_export_f(const void* g, int store, long long offset, long long count, int nz,
+                           long long plane2d, double* out, hipStream_t s);
 hipError_t launch_export_planes(const void* g, int store, int nx, int ny, int nz, int x0, int x1,
                                double* out, hipStream_t s);
-hipError_t launch_import_f(const double* f, int store, long long offset, long long count,
-                           long long plane, void* g, hipStream_t s);
+hipError_t launch_import_f(const double* f, int store, long long offset, long long count, int nz,
+                           long long plane2d, void* g, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, unsigned long long bytes, hipStream_t s);
 
 }  // namespace stglbm

@@ -143,6 +143,7 @@ class Lattice:
     def state_view(self):
         """Torch view (19, NZ, NY, NX) of the current deviations g on the device.
 
+        The device store is [NZ][19][NY][NX]; the view permutes it (no copy).
         FP32 stores give float32; FP16/BF16 stores give float16/bfloat16.
         Valid until the next step or restore.
         """
@@ -151,7 +152,7 @@ class Lattice:
         off = ptr.value - self.workspace.data_ptr()
         dt = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}[self.desc.store]
         raw = self.workspace[off: off + nb.value]
-        return raw.view(dt).view(19, self.nz, self.ny, self.nx)
+        return raw.view(dt).view(self.nz, 19, self.ny, self.nx).permute(1, 0, 2, 3)
 
     def set_f(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64)

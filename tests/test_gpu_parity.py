@@ -157,6 +157,34 @@ def test_ragged_inlet_channel_parity(shape):
     lat.close()
 
 
+@pytest.mark.parametrize("store", ["f32", "f16"])
+def test_cells_per_lane_variants(store, monkeypatch):
+    """Every lane width (1, 2 or 4 x cells per lane) gives the same lattice.
+
+    The per-cell arithmetic does not depend on how many cells a lane owns, so
+    the three launch shapes must agree bit for bit; the FP32 runs must also
+    meet the oracle bar.  48 cells per row: one tile of 48, 24 or 12 lanes.
+    """
+    cfg = small_channel(48, 12, 8, n_modes=20, seed=6, store=store)
+    ora = OracleChannel.from_config(cfg)
+    ora.step(40)
+    runs = {}
+    for vec in (1, 2, 4):
+        monkeypatch.setenv("STGLBM_SHAPE", f"2,1,0,{vec}")
+        lat = _lat(cfg, store=store)
+        lat.step(40)
+        runs[vec] = lat.get_f()
+        lat.close()
+        rel = _rel(runs[vec], ora.f)
+        print(f"[gpu] {store} vec={vec}: max rel err vs oracle {rel.max():.3e}", flush=True)
+        if store == "f32":
+            assert rel.max() < FP32_F_TOL
+    for vec in (2, 4):
+        diff = np.abs(runs[vec] - runs[1]).max()
+        print(f"[gpu] {store} vec={vec} vs vec=1: max abs diff {diff:.3e}", flush=True)
+        assert diff == 0.0
+
+
 @pytest.mark.parametrize("cfg_index,steps", [(1, 8), (3, 4)])
 def test_full_size_front_parity(cfg_index, steps):
     """Full-size lattice in the bench's launch shape, checked where the oracle can follow it.
