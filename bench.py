@@ -6,7 +6,9 @@ FP64 statistics), on the 512x128x256 Re_tau = 180 channel (600 modes, RANS
 input on a 96-cell stretched grid).  Inputs are resident in HBM; W warm-up
 steps run first, then exactly K steps are timed between two device
 synchronizations.  The FP16- and BF16-store variants of the same workload
-are timed the same way.  Prints one JSON line.
+and the 1024x256x512 FP16 lattice are timed the same way; optional legs
+compare long-run FP16/BF16 statistics with FP32 (--precision-steps) and run
+the 64-job serving mix.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -89,6 +91,48 @@ def run_variant(cfg, store, steps, warmup, stats=True):
     return out
 
 
+def precision_study(cfg, steps, warmup):
+    """Long runs of the FP16 and BF16 stores against the FP32 store: profile errors over 2 <= x/delta < 3.5."""
+    import torch
+    from paper_2205_02774_amd import channel_from_config
+    from paper_2205_02774_amd.statistics import profiles, profile_errors
+    d = cfg["ny"] // 2
+    prof = {}
+    for store in ("f32", "f16", "bf16"):
+        t0 = time.perf_counter()
+        lat = channel_from_config(cfg, store=store, device="cuda:0")
+        for k in range(0, warmup, 5000):
+            lat.step(min(5000, warmup - k))
+            lat.sync()
+        lat.stats_reset()
+        for k in range(0, steps, 5000):
+            lat.step(min(5000, steps - k))
+            lat.sync()
+        st, n = lat.get_stats()
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+        prof[store] = profiles(st, n, cfg["nz"], 2 * d, int(3.5 * d))
+        log(f"[bench] precision run {store}: {warmup} + {steps} steps in {time.perf_counter() - t0:.1f} s")
+    out = {"warmup": warmup, "sampled_steps": steps, "x_range_delta": [2.0, 3.5], "reference": "f32"}
+    for store in ("f16", "bf16"):
+        out[store] = {k: round(v, 5) for k, v in profile_errors(prof[store], prof["f32"]).items()}
+    log(f"[bench] precision: {out}")
+    return out
+
+
+def large_lattice(name, steps, warmup):
+    """The largest single-GPU lattice (FP16 store), timed like the main workload."""
+    from workloads import channel_config
+    cfg = channel_config(name)
+    r = run_variant(cfg, cfg["store"], steps, warmup)
+    return {"workload": cfg["name"], "store": cfg["store"], "cells": cfg["cells"], "steps": steps,
+            "warmup": warmup, "value": round(r["mlups"], 1), "unit": "MLUPS",
+            "ms_per_step": round(r["ms_per_step"], 5), "step_kernel_ms": round(r["step_kernel_ms"], 5),
+            "stg_kernel_ms": round(r["stg_kernel_ms"], 5), "achieved_gbs": round(r["achieved_gbs"], 1),
+            "roofline_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4)}
+
+
 def serving_mix(scale, budget_gib, max_active, chunk):
     """The 64-job serving mix with step budgets scaled by `scale` (Poisson arrivals, 2/s)."""
     from paper_2205_02774_amd.serve import Server, DeviceExecutor
@@ -154,6 +198,11 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=24.0)
     ap.add_argument("--serve-max-active", type=int, default=16)
     ap.add_argument("--serve-chunk", type=int, default=250)
+    ap.add_argument("--large", default="channel-1024x256x512-f16", help="large lattice timed after the main one ('' = skip)")
+    ap.add_argument("--large-steps", type=int, default=500)
+    ap.add_argument("--large-warmup", type=int, default=1000)
+    ap.add_argument("--precision-steps", type=int, default=0,
+                    help="if > 0: sampled steps of the FP16/BF16-vs-FP32 profile comparison (after 20k warm-up)")
     ap.add_argument("--cpu-nz", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=4)
     args = ap.parse_args()
@@ -184,6 +233,8 @@ def main():
             "speedup_vs_f32": round(r["mlups"] / main_run["mlups"], 3),
             "warmup": args.variant_warmup,
         }
+    large = large_lattice(args.large, args.large_steps, args.large_warmup) if args.large else None
+    precision = precision_study(cfg, args.precision_steps, 20000) if args.precision_steps > 0 else None
     serving = None
     if args.serve_scale > 0:
         serving = serving_mix(args.serve_scale, args.serve_budget_gib, args.serve_max_active, args.serve_chunk)
@@ -220,6 +271,8 @@ def main():
             "stg_kernel_ms": round(main_run["stg_kernel_ms"], 5),
         },
         "variants": variants,
+        "large": large,
+        "precision": precision,
         "serving": serving,
         "cpu_baseline": cpu,
     }
