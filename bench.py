@@ -121,6 +121,36 @@ def precision_study(cfg, steps, warmup):
     return out
 
 
+def periodic_reference(nx, ny, nz, steps, warmup):
+    """The force-driven periodic reference channel (no inlet plane), FP32, statistics every timed step."""
+    import torch
+    from paper_2205_02774_amd import periodic_channel_from_config
+    from workloads import periodic_channel
+    cfg = periodic_channel(nx, ny, nz, seed=5)
+    lat = periodic_channel_from_config(cfg, device="cuda:0")
+    lat.step(warmup)
+    lat.sync()
+    lat.stats_reset()
+    lat.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat.step(steps)
+    lat.sync()
+    elapsed = time.perf_counter() - t1
+    prof = lat.profile_read()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    cells = nx * ny * nz
+    k_ms = prof["step_ms"] / prof["step_launches"]
+    gbs = 152 * cells / (k_ms * 1e-3) / 1e9
+    log(f"[bench] periodic {cfg['name']}: {1e3 * elapsed / steps:.4f} ms/step, step kernel {k_ms:.4f} ms = {gbs:.0f} GB/s")
+    return {"workload": cfg["name"], "store": "f32", "force": "Guo, 1 m/s^2 along x", "steps": steps,
+            "warmup": warmup, "value": round(cells * steps / elapsed / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(1e3 * elapsed / steps, 5), "step_kernel_ms": round(k_ms, 5),
+            "achieved_gbs": round(gbs, 1), "roofline_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def large_lattice(name, steps, warmup):
     """The largest single-GPU lattice (FP16 store), timed like the main workload."""
     from workloads import channel_config
@@ -201,6 +231,8 @@ def main():
     ap.add_argument("--large", default="channel-1024x256x512-f16", help="large lattice timed after the main one ('' = skip)")
     ap.add_argument("--large-steps", type=int, default=500)
     ap.add_argument("--large-warmup", type=int, default=1000)
+    ap.add_argument("--periodic-steps", type=int, default=500,
+                    help="timed steps of the periodic force-driven 512x128x256 reference channel (0 = skip)")
     ap.add_argument("--precision-steps", type=int, default=0,
                     help="if > 0: sampled steps of the FP16/BF16-vs-FP32 profile comparison (after 20k warm-up)")
     ap.add_argument("--cpu-nz", type=int, default=32)
@@ -234,6 +266,8 @@ def main():
             "warmup": args.variant_warmup,
         }
     large = large_lattice(args.large, args.large_steps, args.large_warmup) if args.large else None
+    periodic = periodic_reference(cfg["nx"], cfg["ny"], cfg["nz"], args.periodic_steps, 500) \
+        if args.periodic_steps > 0 else None
     precision = precision_study(cfg, args.precision_steps, 20000) if args.precision_steps > 0 else None
     serving = None
     if args.serve_scale > 0:
@@ -272,6 +306,7 @@ def main():
         },
         "variants": variants,
         "large": large,
+        "periodic": periodic,
         "precision": precision,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -169,6 +169,13 @@ int stglbm_state_view(stglbm_t h, void** d_g, uint64_t* bytes);
 /* Replace the distributions by f (rounded to the store type). Synchronizes. */
 int stglbm_set_f(stglbm_t h, const double* h_in, uint64_t n);
 
+/* Replace the distributions by the equilibrium f_eq(rho = 1, u) of eq.
+ * local_eq, from a host velocity field u [3][NZ][NY][NX] (lattice units,
+ * FP64; component-major), computed in FP64 and rounded to the store type.
+ * Used to start a run from a velocity profile (e.g. the periodic reference
+ * channel).  n must be 3*NX*NY*NZ.  Synchronizes. */
+int stglbm_set_equilibrium(stglbm_t h, const double* h_u, uint64_t n);
+
 /* Mode table [N][8]: k^n, d^n (3), sigma^n (3), phi^n (FP64). Synchronizes. */
 int stglbm_get_modes(stglbm_t h, double* h_out, uint64_t n);
 /* Per-row inlet table [NY][STGLBM_ROW_FIELDS] FP64. Synchronizes. */

@@ -52,6 +52,24 @@ class OracleChannel:
                               cfg["n_modes"], cfg["alpha"], cfg["seed"], cfg["C_l"], cfg["C_mu"])
         return ch
 
+    @classmethod
+    def periodic_from_config(cls, cfg):
+        """The force-driven periodic reference channel (Numerical setup: periodic
+        LES-LBM channel with a body force).  The physical acceleration and the
+        start velocity are converted to lattice units (force F c_t^2/c_x,
+        velocity u c_t/c_x) and the start state is f_eq(1, u) (eq. local_eq)."""
+        rans = cfg["rans"]
+        c_x, c_t, nu_lb, _ = units.channel_units(cfg["delta"], cfg["ny"], cfg["u_b_lb"],
+                                                 rans["U_b"], cfg["nu_phys"])
+        force = tuple(units.acceleration_to_lattice(a, c_t, c_x) for a in cfg["force_phys"])
+        ch = cls(cfg["nx"], cfg["ny"], cfg["nz"], nu_lb=nu_lb, cs_smag=cfg["cs_smag"], force=force,
+                 periodic_x=True)
+        ch.c_x, ch.c_t = c_x, c_t
+        u0 = cfg["u_b_lb"] * np.asarray(cfg["start_perturbation"], dtype=np.float64)
+        u0[0] += units.velocity_to_lattice(rans["U3"][:, 0], c_t, c_x)[None, :, None]
+        ch.set_f(L.equilibrium(np.ones(u0.shape[1:]), u0))
+        return ch
+
     def set_rans_inlet(self, rans, delta, c_x, c_t, nu_phys, U_b, n_modes, alpha, seed,
                        C_l=3.0, C_mu=0.09):
         self.inlet = InletGenerator(rans, self.ny, self.nz, delta, c_x, c_t, nu_phys, U_b,

@@ -522,6 +522,22 @@ int stglbm_set_f(stglbm_t h, const double* h_in, uint64_t n) {
   return STGLBM_OK;
 }
 
+int stglbm_set_equilibrium(stglbm_t h, const double* h_u, uint64_t n) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  const uint64_t total = 3ull * h->cells();
+  if (!h_u || n != total) return fail(h, STGLBM_E_INVAL, "u buffer must hold 3*NX*NY*NZ doubles");
+  const int rc = sync_and_check(h);
+  if (rc != STGLBM_OK && rc != STGLBM_E_UNSTABLE) return rc;
+  // staged in the idle distribution buffer (19 s >= 24 bytes per cell for every store type)
+  double* stage = static_cast<double*>(h->gbuf(1 - h->cur));
+  HIP_CHECK(h, hipMemcpyAsync(stage, h_u, total * sizeof(double), hipMemcpyHostToDevice, h->stream), "hipMemcpyAsync u");
+  HIP_CHECK(h, launch_equilibrium(stage, h->d.store, h->d.nx, h->d.ny, h->d.nz, h->gbuf(h->cur), h->stream),
+            "equilibrium kernel");
+  HIP_CHECK(h, launch_fill_zero(h->at<char>(h->L.flag), kAlign, h->stream), "flag reset");
+  HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  return STGLBM_OK;
+}
+
 static int copy_out(stglbm_t h, uint64_t off, uint64_t bytes, double* out) {
   const int rc = sync_and_check(h);
   HIP_CHECK(h, hipMemcpy(out, h->ws + off, bytes, hipMemcpyDeviceToHost), "hipMemcpy");

@@ -604,6 +604,24 @@ __global__ void import_f_kernel(const double* f, long long offset, long long cou
   }
 }
 
+// f = f_eq(rho = 1, u) (eq. local_eq) from a velocity field u[3][NZ][NY][NX]
+// in lattice units, computed in FP64 and rounded once to the store type.
+template <class Codec>
+__global__ void equilibrium_kernel(const double* u, int nx, int ny, int nz, typename Codec::storage* g) {
+  const long long plane2d = (long long)nx * ny;
+  const long long cells = plane2d * nz;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += stride) {
+    const double ux = u[c], uy = u[cells + c], uz = u[2 * cells + c];
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const long long z = c / plane2d, yx = c - z * plane2d;
+    for (int i = 0; i < kQ; ++i) {
+      const double cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+      g[(z * kQ + i) * plane2d + yx] = Codec::encode(static_cast<float>(weight_d(i) * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu)));
+    }
+  }
+}
+
 int grid_for(unsigned long long n, int block) {
   unsigned long long b = (n + block - 1) / block;
   if (b > 65536ull * 4) b = 65536ull * 4;
@@ -702,6 +720,17 @@ hipError_t launch_import_f(const double* f, int store, long long offset, long lo
     case 0: import_f_kernel<CodecF32><<<grid, 256, 0, s>>>(f, offset, count, nz, plane2d, static_cast<float*>(g)); break;
     case 1: import_f_kernel<CodecF16><<<grid, 256, 0, s>>>(f, offset, count, nz, plane2d, static_cast<unsigned short*>(g)); break;
     case 2: import_f_kernel<CodecBF16><<<grid, 256, 0, s>>>(f, offset, count, nz, plane2d, static_cast<unsigned short*>(g)); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_equilibrium(const double* u, int store, int nx, int ny, int nz, void* g, hipStream_t s) {
+  const int grid = grid_for(static_cast<unsigned long long>(nx) * ny * nz, 256);
+  switch (store) {
+    case 0: equilibrium_kernel<CodecF32><<<grid, 256, 0, s>>>(u, nx, ny, nz, static_cast<float*>(g)); break;
+    case 1: equilibrium_kernel<CodecF16><<<grid, 256, 0, s>>>(u, nx, ny, nz, static_cast<unsigned short*>(g)); break;
+    case 2: equilibrium_kernel<CodecBF16><<<grid, 256, 0, s>>>(u, nx, ny, nz, static_cast<unsigned short*>(g)); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

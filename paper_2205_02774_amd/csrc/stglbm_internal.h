@@ -90,6 +90,7 @@ hipError_t launch_export_planes(const void* g, int store, int nx, int ny, int nz
                                double* out, hipStream_t s);
 hipError_t launch_import_f(const double* f, int store, long long offset, long long count, int nz,
                            long long plane2d, void* g, hipStream_t s);
+hipError_t launch_equilibrium(const double* u, int store, int nx, int ny, int nz, void* g, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, unsigned long long bytes, hipStream_t s);
 
 }  // namespace stglbm

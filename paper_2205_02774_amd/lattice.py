@@ -160,6 +160,13 @@ class Lattice:
             raise ValueError("f must have shape (19, NZ, NY, NX)")
         self._chk(self.lib.stglbm_set_f(self.handle, _dptr(f), f.size))
 
+    def set_equilibrium(self, u):
+        """Distributions = f_eq(rho = 1, u) for a velocity field u of shape (3, NZ, NY, NX), lattice units."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        if u.shape != (3, self.nz, self.ny, self.nx):
+            raise ValueError("u must have shape (3, NZ, NY, NX)")
+        self._chk(self.lib.stglbm_set_equilibrium(self.handle, _dptr(u), u.size))
+
     def get_modes(self):
         out = np.empty((self.n_modes, 8))
         self._chk(self.lib.stglbm_get_modes(self.handle, _dptr(out), out.size))
@@ -232,4 +239,23 @@ def channel_from_config(cfg, *, store=None, device="cuda", stream=None, periodic
         lat.set_rans_inlet(rans, delta=cfg["delta"], nu_phys=cfg["nu_phys"], c_x=c_x, c_t=c_t, U_b=rans["U_b"],
                            n_modes=n_modes, alpha=cfg["alpha"], seed=cfg["seed"], C_l=cfg["C_l"],
                            C_mu=cfg["C_mu"])
+    return lat
+
+
+def periodic_channel_from_config(cfg, *, store=None, device="cuda", stream=None):
+    """Build the force-driven periodic reference channel of a `workloads.periodic_channel` configuration.
+
+    Units come from the library (`stglbm_derive_units`); the physical
+    acceleration and the start velocity are converted with them (a = F c_t^2 / c_x,
+    u = u_phys c_t / c_x) and the start state is f_eq of that velocity.
+    """
+    rans = cfg["rans"]
+    c_x, c_t, nu_lb = derive_units(cfg["delta"], cfg["ny"], cfg["u_b_lb"], rans["U_b"], cfg["nu_phys"])
+    force = tuple(a * c_t * c_t / c_x for a in cfg["force_phys"])
+    lat = Lattice(cfg["nx"], cfg["ny"], cfg["nz"], device=device, stream=stream, store=store or cfg["store"],
+                  periodic_x=True, nu_lb=nu_lb, cs_smag=cfg["cs_smag"], force=force)
+    lat.c_x, lat.c_t, lat.nu_lb, lat.force = c_x, c_t, nu_lb, force
+    u0 = cfg["u_b_lb"] * np.asarray(cfg["start_perturbation"], dtype=np.float64)
+    u0[0] += (rans["U3"][:, 0] * c_t / c_x)[None, :, None]
+    lat.set_equilibrium(u0)
     return lat

@@ -334,3 +334,25 @@ def test_laminar_inlet_outlet_steady_mass_flux():
     # the outlet keeps its density and no tangential velocity
     np.testing.assert_allclose(ch.last_rho[:, :, -1], 1.0, rtol=1e-13)
     np.testing.assert_allclose(ch.last_u[1:, :, :, -1], 0.0, atol=1e-15)
+
+
+def test_periodic_reference_start_state():
+    """The periodic reference channel starts from f_eq(1, u0): its moments return
+    rho = 1 and u0 exactly (equilibrium moments), u0 = RANS U(y) c_t/c_x + perturbation,
+    and the body force is a c_t^2/c_x for a = 1 m/s^2 (eq. of the unit conversion)."""
+    from workloads import periodic_channel
+    from oracle import units
+    cfg = periodic_channel(12, 8, 4, seed=1)
+    ch = OracleChannel.periodic_from_config(cfg)
+    rho = L.density(ch.f)
+    u = np.einsum("ia,i...->a...", L.C.astype(np.float64), ch.f) / rho
+    c_x, c_t, _, _ = units.channel_units(cfg["delta"], cfg["ny"], cfg["u_b_lb"], cfg["rans"]["U_b"], cfg["nu_phys"])
+    u0 = cfg["u_b_lb"] * cfg["start_perturbation"]
+    u0[0] += (cfg["rans"]["U3"][:, 0] * c_t / c_x)[None, :, None]
+    np.testing.assert_allclose(rho, 1.0, atol=1e-14)
+    np.testing.assert_allclose(u, u0, atol=1e-15)
+    assert ch.force[0] == pytest.approx(c_t ** 2 / c_x, rel=1e-15)
+    assert ch.periodic_x
+    m0 = ch.f.sum()
+    ch.step(5)
+    assert ch.f.sum() == pytest.approx(m0, rel=1e-13)

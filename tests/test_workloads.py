@@ -72,3 +72,15 @@ def test_serving_jobs_seeded():
     assert np.mean(np.diff(arr)) == pytest.approx(0.5, rel=0.3)
     assert {j["store"] for j in a} <= {"f32", "f16"}
     assert all(1000 <= j["steps"] <= 20000 for j in a)
+
+
+def test_periodic_channel_config():
+    from workloads import periodic_channel
+    a = periodic_channel(24, 16, 8, seed=3)
+    b = periodic_channel(24, 16, 8, seed=3)
+    assert a["periodic_x"] and a["sponge_cells"] == 0
+    assert a["force_phys"] == (1.0, 0.0, 0.0)            # u_tau^2 / delta with u_tau = delta = 1
+    assert a["start_perturbation"].shape == (3, 8, 16, 24)
+    np.testing.assert_array_equal(a["start_perturbation"], b["start_perturbation"])
+    assert np.abs(a["start_perturbation"]).max() <= 0.1
+    assert a["rans"]["U3"].shape[0] == 16

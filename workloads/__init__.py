@@ -20,7 +20,8 @@ from .rans import (
     channel_rans_profile,
     bulk_velocity_fv,
 )
-from .configs import channel_config, CONFIG_NAMES, perturbed_state, serving_jobs, job_config, small_channel
+from .configs import (channel_config, CONFIG_NAMES, perturbed_state, serving_jobs, job_config, small_channel,
+                      periodic_channel)
 
 __all__ = [
     "KAPPA",
@@ -37,4 +38,5 @@ __all__ = [
     "serving_jobs",
     "job_config",
     "small_channel",
+    "periodic_channel",
 ]

@@ -73,6 +73,28 @@ def small_channel(nx, ny, nz, re_tau=180.0, n_modes=50, alpha=0.05, seed=0, stor
     return cfg
 
 
+def periodic_channel(nx, ny, nz, re_tau=180.0, store="f32", seed=0, amplitude=0.1):
+    """Channel periodic in x and z, driven by the mean pressure gradient as a body force.
+
+    This is the paper's LES-LBM reference set-up (periodic channel with a
+    body force in place of the inlet and outlet).  The force is the physical
+    acceleration u_tau^2 / delta = 1 m/s^2 along x that balances the wall
+    shear in the mean.  The start state is the RANS mean velocity at the
+    lattice rows plus a seeded perturbation: `start_perturbation` holds
+    uniform numbers in (-amplitude, amplitude) of shape (3, NZ, NY, NX), to be
+    scaled by the lattice bulk velocity.
+    """
+    cfg = dict(nx=nx, ny=ny, nz=nz, store=store, re_tau=re_tau, n_modes=0, alpha=0.0, seed=seed,
+               name=f"periodic-{nx}x{ny}x{nz}", periodic_x=True)
+    cfg["rans"] = _rans_on_rows(ny, re_tau)
+    cfg["force_phys"] = (1.0, 0.0, 0.0)
+    rng = np.random.default_rng(seed)
+    cfg["start_perturbation"] = rng.uniform(-amplitude, amplitude, size=(3, nz, ny, nx))
+    _common(cfg)
+    cfg["sponge_cells"] = 0
+    return cfg
+
+
 def _common(cfg):
     cfg.setdefault("delta", 1.0)
     cfg.setdefault("u_tau", 1.0)
