@@ -21,6 +21,8 @@ import subprocess
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -151,6 +153,52 @@ def periodic_reference(nx, ny, nz, steps, warmup):
             "achieved_gbs": round(gbs, 1), "roofline_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def adaptation_study(cfg, steps, warmup):
+    """Adaptation diagnostics of the FP32 STG channel: u_tau(x) / u_theory from the FP64
+    statistics (eq. u_shear), the adaptation length (first x/delta from which it stays within
+    +-3 % up to the sponge), and the integral time scale T_t (eq. time-integral) of u at
+    y+ ~ 100 probes at x/delta = 0, 1, 2, 4, ... (z = NZ/2), in units of t* = delta / U_bulk."""
+    import torch
+    from paper_2205_02774_amd import channel_from_config
+    from paper_2205_02774_amd.statistics import friction_velocity, adaptation_length, autocorrelation, \
+        integral_time
+    d = cfg["ny"] // 2
+    yplus_per_cell = cfg["re_tau"] / d
+    j100 = int(round(100.0 / yplus_per_cell - 0.5))
+    stations = [s for s in (0, 1, 2, 4, 8, 16) if s * d < cfg["nx"] - cfg["sponge_cells"]]
+    cells = [(s * d, j100, cfg["nz"] // 2) for s in stations]
+    t0 = time.perf_counter()
+    lat = channel_from_config(cfg, store="f32", device="cuda:0")
+    for k in range(0, warmup, 5000):
+        lat.step(min(5000, warmup - k))
+        lat.sync()
+    lat.stats_reset()
+    series = lat.set_probes(cells, steps)
+    for k in range(0, steps, 5000):
+        lat.step(min(5000, steps - k))
+        lat.sync()
+    st, n = lat.get_stats()
+    u = series.cpu().numpy().astype(np.float64)
+    u_theory = lat.c_t / lat.c_x                       # u_tau = 1 m/s in lattice units
+    ratio = friction_velocity(st, n, cfg["nz"], lat.nu_lb) / u_theory
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    x_d = np.arange(cfg["nx"]) / d
+    t_star = d / cfg["u_b_lb"]                         # t* = delta / U_bulk, in steps
+    out = {"warmup": warmup, "sampled_steps": steps, "u_theory_lb": u_theory,
+           "adaptation_length_delta": adaptation_length(ratio, x_d, 0.03, (cfg["nx"] - cfg["sponge_cells"]) / d),
+           "u_tau_ratio_at": {f"{s}": round(float(ratio[min(s * d, cfg['nx'] - 1)]), 4) for s in (1, 2, 3, 4, 6)
+                              if s * d < cfg["nx"]},
+           "probe_y_plus": round((j100 + 0.5) * yplus_per_cell, 1),
+           "t_star_steps": t_star,
+           "T_t_over_t_star": {f"{s}": round(float(integral_time(autocorrelation(u[:, k, 0]), 1.0)) / t_star, 4)
+                               for k, s in enumerate(stations)},
+           "record_t_star": round(steps / t_star, 3)}
+    log(f"[bench] adaptation: {out} ({time.perf_counter() - t0:.1f} s)")
+    return out
+
+
 def large_lattice(name, steps, warmup):
     """The largest single-GPU lattice (FP16 store), timed like the main workload."""
     from workloads import channel_config
@@ -233,6 +281,8 @@ def main():
     ap.add_argument("--large-warmup", type=int, default=1000)
     ap.add_argument("--periodic-steps", type=int, default=500,
                     help="timed steps of the periodic force-driven 512x128x256 reference channel (0 = skip)")
+    ap.add_argument("--adaptation-steps", type=int, default=0,
+                    help="if > 0: sampled steps of the u_tau(x) / probe autocorrelation study (after 20k warm-up)")
     ap.add_argument("--precision-steps", type=int, default=0,
                     help="if > 0: sampled steps of the FP16/BF16-vs-FP32 profile comparison (after 20k warm-up)")
     ap.add_argument("--cpu-nz", type=int, default=32)
@@ -269,6 +319,7 @@ def main():
     periodic = periodic_reference(cfg["nx"], cfg["ny"], cfg["nz"], args.periodic_steps, 500) \
         if args.periodic_steps > 0 else None
     precision = precision_study(cfg, args.precision_steps, 20000) if args.precision_steps > 0 else None
+    adaptation = adaptation_study(cfg, args.adaptation_steps, 20000) if args.adaptation_steps > 0 else None
     serving = None
     if args.serve_scale > 0:
         serving = serving_mix(args.serve_scale, args.serve_budget_gib, args.serve_max_active, args.serve_chunk)
@@ -308,6 +359,7 @@ def main():
         "large": large,
         "periodic": periodic,
         "precision": precision,
+        "adaptation": adaptation,
         "serving": serving,
         "cpu_baseline": cpu,
     }

@@ -176,6 +176,21 @@ int stglbm_set_f(stglbm_t h, const double* h_in, uint64_t n);
  * channel).  n must be 3*NX*NY*NZ.  Synchronizes. */
 int stglbm_set_equilibrium(stglbm_t h, const double* h_u, uint64_t n);
 
+/* Velocity probes (adaptation diagnostics: time series at chosen cells).
+ * After every following step the velocity the collision used at each of the
+ * n cells (x, y, z) = h_xyz[3k..3k+2] (host array, copied) is written, in
+ * FP32 lattice units, to row r of the caller's device buffer d_series
+ * [capacity][n][3], r = 0, 1, ... until capacity rows are written; the
+ * velocity is recovered from the post-collision state as
+ * (sum_i c_i f_i - F/2) / sum_i f_i.  The buffer must stay valid while
+ * probes are set.  n = 0 turns probes off.  Asynchronous (one small kernel
+ * per step on the handle's stream).  Errors: n outside 0..64, a cell outside
+ * the lattice, null pointers or capacity < 1 give STGLBM_E_INVAL. */
+#define STGLBM_MAX_PROBES 64
+int stglbm_set_probes(stglbm_t h, int32_t n, const int32_t* h_xyz, float* d_series, int64_t capacity);
+/* Number of probe rows written so far (enqueued; synchronize before reading). */
+int stglbm_probe_rows(stglbm_t h, int64_t* rows);
+
 /* Mode table [N][8]: k^n, d^n (3), sigma^n (3), phi^n (FP64). Synchronizes. */
 int stglbm_get_modes(stglbm_t h, double* h_out, uint64_t n);
 /* Per-row inlet table [NY][STGLBM_ROW_FIELDS] FP64. Synchronizes. */

@@ -163,6 +163,10 @@ struct stglbm_ctx {
   std::string err;
   bool prof = false;
   std::vector<hipEvent_t> ev_step, ev_stg;   // start/stop pairs
+  int n_probes = 0;                           // velocity probes (caller's device buffer)
+  int probe_xyz[kMaxProbes][3] = {};
+  float* probe_out = nullptr;
+  int64_t probe_capacity = 0, probe_rows = 0;
   size_t n_step = 0, n_stg = 0;
 
   template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -425,7 +429,51 @@ int stglbm_step(stglbm_t h, int32_t n_steps) {
     h->cur = 1 - h->cur;
     ++h->t;
     if (h->sampling) ++h->n_samples;
+    if (h->n_probes > 0 && h->probe_rows < h->probe_capacity) {
+      ProbeParams q{};
+      q.g = h->gbuf(h->cur);
+      q.plane2d = static_cast<long long>(h->d.nx) * h->d.ny;
+      q.nx = h->d.nx;
+      q.n = h->n_probes;
+      q.fx = h->d.force[0];
+      q.fy = h->d.force[1];
+      q.fz = h->d.force[2];
+      std::memcpy(q.xyz, h->probe_xyz, sizeof(q.xyz));
+      q.out = h->probe_out + 3 * h->n_probes * h->probe_rows;
+      HIP_CHECK(h, launch_probes(q, h->d.store, h->stream), "probe kernel launch");
+      ++h->probe_rows;
+    }
   }
+  return STGLBM_OK;
+}
+
+int stglbm_set_probes(stglbm_t h, int32_t n, const int32_t* h_xyz, float* d_series, int64_t capacity) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  if (n == 0) {
+    h->n_probes = 0;
+    h->probe_out = nullptr;
+    h->probe_capacity = h->probe_rows = 0;
+    return STGLBM_OK;
+  }
+  if (n < 0 || n > kMaxProbes) return fail(h, STGLBM_E_INVAL, "number of probes must be 0..64");
+  if (!h_xyz || !d_series || capacity < 1) return fail(h, STGLBM_E_INVAL, "null probe list or series, or capacity < 1");
+  for (int k = 0; k < n; ++k) {
+    const int x = h_xyz[3 * k], y = h_xyz[3 * k + 1], z = h_xyz[3 * k + 2];
+    if (x < 0 || x >= h->d.nx || y < 0 || y >= h->d.ny || z < 0 || z >= h->d.nz)
+      return fail(h, STGLBM_E_INVAL, "probe outside the lattice");
+  }
+  for (int k = 0; k < n; ++k)
+    for (int a = 0; a < 3; ++a) h->probe_xyz[k][a] = h_xyz[3 * k + a];
+  h->n_probes = n;
+  h->probe_out = d_series;
+  h->probe_capacity = capacity;
+  h->probe_rows = 0;
+  return STGLBM_OK;
+}
+
+int stglbm_probe_rows(stglbm_t h, int64_t* rows) {
+  if (!h || !rows) return fail(h, STGLBM_E_INVAL, "null handle or output");
+  *rows = h->probe_rows;
   return STGLBM_OK;
 }
 

@@ -622,6 +622,28 @@ __global__ void equilibrium_kernel(const double* u, int nx, int ny, int nz, type
   }
 }
 
+// Velocity of the collision at the probe cells, recovered from the
+// post-collision state: collision keeps rho and returns sum c f = rho u + F/2
+// (regularized operator with J_neq = -F/2 plus the Guo source).  FP64 sums.
+template <class Codec>
+__global__ void probe_kernel(ProbeParams p) {
+  const int k = threadIdx.x;
+  if (k >= p.n) return;
+  const auto* g = static_cast<const typename Codec::storage*>(p.g);
+  const long long base = (long long)p.xyz[k][2] * kQ * p.plane2d + (long long)p.xyz[k][1] * p.nx + p.xyz[k][0];
+  double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+  for (int i = 0; i < kQ; ++i) {
+    const double f = weight_d(i) + static_cast<double>(Codec::decode(g[base + i * p.plane2d]));
+    rho += f;
+    jx += CX[i] * f;
+    jy += CY[i] * f;
+    jz += CZ[i] * f;
+  }
+  p.out[3 * k + 0] = static_cast<float>((jx - 0.5 * p.fx) / rho);
+  p.out[3 * k + 1] = static_cast<float>((jy - 0.5 * p.fy) / rho);
+  p.out[3 * k + 2] = static_cast<float>((jz - 0.5 * p.fz) / rho);
+}
+
 int grid_for(unsigned long long n, int block) {
   unsigned long long b = (n + block - 1) / block;
   if (b > 65536ull * 4) b = 65536ull * 4;
@@ -731,6 +753,17 @@ hipError_t launch_equilibrium(const double* u, int store, int nx, int ny, int nz
     case 0: equilibrium_kernel<CodecF32><<<grid, 256, 0, s>>>(u, nx, ny, nz, static_cast<float*>(g)); break;
     case 1: equilibrium_kernel<CodecF16><<<grid, 256, 0, s>>>(u, nx, ny, nz, static_cast<unsigned short*>(g)); break;
     case 2: equilibrium_kernel<CodecBF16><<<grid, 256, 0, s>>>(u, nx, ny, nz, static_cast<unsigned short*>(g)); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_probes(const ProbeParams& p, int store, hipStream_t s) {
+  if (p.n < 1 || p.n > kMaxProbes) return hipErrorInvalidValue;
+  switch (store) {
+    case 0: probe_kernel<CodecF32><<<1, 64, 0, s>>>(p); break;
+    case 1: probe_kernel<CodecF16><<<1, 64, 0, s>>>(p); break;
+    case 2: probe_kernel<CodecBF16><<<1, 64, 0, s>>>(p); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -47,6 +47,17 @@ struct StepParams {
   int* flag;
 };
 
+// Velocity probes: after a step, u at up to kMaxProbes cells of the new state.
+constexpr int kMaxProbes = 64;
+struct ProbeParams {
+  const void* g;            // state just written, [NZ][19][NY][NX]
+  long long plane2d;        // NX*NY
+  int nx, n;
+  double fx, fy, fz;        // Guo acceleration (u = (sum c f - F/2) / rho)
+  int xyz[kMaxProbes][3];
+  float* out;               // this step's row of the series: [n][3]
+};
+
 // STG inlet plane, one launch per time step.
 struct StgParams {
   const double* modes;      // [N][8]
@@ -91,6 +102,7 @@ hipError_t launch_export_planes(const void* g, int store, int nx, int ny, int nz
 hipError_t launch_import_f(const double* f, int store, long long offset, long long count, int nz,
                            long long plane2d, void* g, hipStream_t s);
 hipError_t launch_equilibrium(const double* u, int store, int nx, int ny, int nz, void* g, hipStream_t s);
+hipError_t launch_probes(const ProbeParams& p, int store, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, unsigned long long bytes, hipStream_t s);
 
 }  // namespace stglbm

@@ -167,6 +167,30 @@ class Lattice:
             raise ValueError("u must have shape (3, NZ, NY, NX)")
         self._chk(self.lib.stglbm_set_equilibrium(self.handle, _dptr(u), u.size))
 
+    def set_probes(self, cells, capacity):
+        """Record u at `cells` ((x, y, z) triples, at most 64) after each of the next `capacity` steps.
+
+        Returns the device tensor (capacity, n, 3) float32 the library writes into.
+        """
+        import torch
+        xyz = np.ascontiguousarray(np.asarray(cells, dtype=np.int32).reshape(-1, 3))
+        series = torch.zeros((int(capacity), len(xyz), 3), dtype=torch.float32, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()   # the fill must land before the library's writes
+        self._chk(self.lib.stglbm_set_probes(self.handle, len(xyz),
+                                             xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             ctypes.c_void_p(series.data_ptr()), int(capacity)))
+        self._probe_series = series          # keep the buffer alive while the library writes it
+        return series
+
+    def probe_rows(self):
+        rows = ctypes.c_int64()
+        self._chk(self.lib.stglbm_probe_rows(self.handle, ctypes.byref(rows)))
+        return rows.value
+
+    def clear_probes(self):
+        self._chk(self.lib.stglbm_set_probes(self.handle, 0, None, None, 0))
+        self._probe_series = None
+
     def get_modes(self):
         out = np.empty((self.n_modes, 8))
         self._chk(self.lib.stglbm_get_modes(self.handle, _dptr(out), out.size))
