@@ -18,7 +18,7 @@ from .stg import InletGenerator
 class OracleChannel:
     def __init__(self, nx, ny, nz, *, nu_lb, cs_smag=0.1, force=(0.0, 0.0, 0.0),
                  periodic_x=False, rho_out=1.0, sponge_cells=0, sponge_K=1000.0, sponge_p=3.0,
-                 periodic_y=False, operator="regularized"):
+                 periodic_y=False, operator="regularized", velocity_set=19):
         self.nx, self.ny, self.nz = nx, ny, nz
         self.nu_lb = nu_lb
         self.tau0 = units.tau_from_nu(nu_lb)
@@ -26,10 +26,11 @@ class OracleChannel:
         self.force = tuple(float(v) for v in force)
         self.periodic_x = periodic_x
         self.periodic_y = periodic_y        # oracle-only self-test option
-        self.operator = operator            # "regularized" or oracle-only "bgk"
+        self.operator = operator            # "regularized" or "bgk" (plain BGK bulk, eq. lbe)
+        self.vs = L.velocity_set(velocity_set)
         self.rho_out = rho_out
         self.sponge = L.sponge_factor(nx, 0 if periodic_x else sponge_cells, sponge_K, sponge_p)
-        self.f = np.broadcast_to(L.W[:, None, None, None], (L.Q, nz, ny, nx)).copy()
+        self.f = np.broadcast_to(self.vs.W[:, None, None, None], (self.vs.Q, nz, ny, nx)).copy()
         self.t = 0
         self.inlet = None
         self.stats = np.zeros((nx, ny, 9))
@@ -38,14 +39,15 @@ class OracleChannel:
         self.guard_violations = 0
 
     @classmethod
-    def from_config(cls, cfg, periodic_x=False):
+    def from_config(cls, cfg, periodic_x=False, operator="regularized", velocity_set=19):
         """Build from a workloads configuration (units derived here, FP64)."""
         rans = cfg["rans"]
         c_x, c_t, nu_lb, _ = units.channel_units(cfg["delta"], cfg["ny"], cfg["u_b_lb"],
                                                  rans["U_b"], cfg["nu_phys"])
         ch = cls(cfg["nx"], cfg["ny"], cfg["nz"], nu_lb=nu_lb, cs_smag=cfg["cs_smag"],
                  force=cfg["force"], periodic_x=periodic_x, rho_out=cfg["rho_out"],
-                 sponge_cells=cfg["sponge_cells"], sponge_K=cfg["sponge_K"], sponge_p=cfg["sponge_p"])
+                 sponge_cells=cfg["sponge_cells"], sponge_K=cfg["sponge_K"], sponge_p=cfg["sponge_p"],
+                 operator=operator, velocity_set=velocity_set)
         ch.c_x, ch.c_t = c_x, c_t
         if not periodic_x:
             ch.set_rans_inlet(rans, cfg["delta"], c_x, c_t, cfg["nu_phys"], rans["U_b"],

@@ -1,5 +1,8 @@
 """D3Q19 lattice-Boltzmann LES, FP64 (test infrastructure, see package header).
 
+Every function also runs on the D3Q15 and D3Q27 sets: the set is taken from
+the leading dimension of the distribution array (or a q argument).
+
 Arrays of distributions are indexed f[i, z, y, x]: population i, spanwise
 z, wall-normal y, streamwise x.  All functions work on whole arrays with
 NumPy broadcasting; nothing is blocked, fused or reordered beyond the
@@ -42,29 +45,57 @@ Readings adopted where the paper is silent or garbled:
 
 import numpy as np
 
-Q = 19
-CS2 = 1.0 / 3.0          # c_s^2 (Methodology: c_s = 1/sqrt(3))
+CS2 = 1.0 / 3.0          # c_s^2 (Methodology: c_s = 1/sqrt(3)); the same for D3Q15, D3Q19 and D3Q27
 CS4 = CS2 * CS2
 
-# D3Q19 velocities: rest, 6 axis directions, 12 face diagonals, ordered so
-# that opposite directions are neighbours (i, i+1) for odd i.
-C = np.array([
-    (0, 0, 0),
-    (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
-    (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0),
-    (1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1),
-    (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1),
-], dtype=np.int64)
-W = np.array([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12)
-OPP = np.array([0] + [i + 1 if i % 2 == 1 else i - 1 for i in range(1, Q)], dtype=np.int64)
+_AXES = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+_FACES = [(1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0),
+          (1, 0, 1), (-1, 0, -1), (1, 0, -1), (-1, 0, 1),
+          (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+_CORNERS = [(1, 1, 1), (-1, -1, -1), (1, 1, -1), (-1, -1, 1),
+            (1, -1, 1), (-1, 1, -1), (-1, 1, 1), (1, -1, -1)]
 
-# Q_i = c_i c_i - c_s^2 I (eq. f_i_neq), shape (19, 3, 3)
-QT = np.einsum("ia,ib->iab", C, C).astype(np.float64) - CS2 * np.eye(3)[None]
+
+class VelocitySet:
+    """A cubic velocity set: rest, then opposite directions as neighbours (i, i+1) for odd i.
+
+    D3Q19 is the method's set (Methodology); D3Q15 and D3Q27 are the variants
+    the method's boundary treatment carries over to (Numerical method, the
+    remark on other velocity sets).  Weights are the standard ones that make
+    the moments isotropic up to fourth order with c_s^2 = 1/3.
+    """
+
+    def __init__(self, name, dirs, weights):
+        self.name = name
+        self.C = np.array([(0, 0, 0)] + dirs, dtype=np.int64)
+        self.Q = len(self.C)
+        self.W = np.array(weights, dtype=np.float64)
+        self.OPP = np.array([0] + [i + 1 if i % 2 == 1 else i - 1 for i in range(1, self.Q)], dtype=np.int64)
+        # Q_i = c_i c_i - c_s^2 I (eq. f_i_neq), shape (Q, 3, 3)
+        self.QT = np.einsum("ia,ib->iab", self.C, self.C).astype(np.float64) - CS2 * np.eye(3)[None]
+        self.INLET_UNKNOWN = self.C[:, 0] == 1
+        self.OUTLET_UNKNOWN = self.C[:, 0] == -1
+
+
+D3Q19 = VelocitySet("D3Q19", _AXES + _FACES, [1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+D3Q15 = VelocitySet("D3Q15", _AXES + _CORNERS, [2 / 9] + [1 / 9] * 6 + [1 / 72] * 8)
+D3Q27 = VelocitySet("D3Q27", _AXES + _FACES + _CORNERS,
+                    [8 / 27] + [2 / 27] * 6 + [1 / 54] * 12 + [1 / 216] * 8)
+VELOCITY_SETS = {15: D3Q15, 19: D3Q19, 27: D3Q27}
+
+
+def velocity_set(q):
+    """The velocity set with q populations (15, 19 or 27)."""
+    return VELOCITY_SETS[int(q)]
+
+
+# The method's set, under the names the rest of the oracle and its pins use.
+Q, C, W, OPP, QT = D3Q19.Q, D3Q19.C, D3Q19.W, D3Q19.OPP, D3Q19.QT
 
 
 def _bc(v, nd):
-    """Broadcast a (19,) table against a field with nd trailing dims."""
-    return v.reshape((Q,) + (1,) * nd)
+    """Broadcast a (Q,) table against a field with nd trailing dims."""
+    return v.reshape((len(v),) + (1,) * nd)
 
 
 def density(f):
@@ -74,38 +105,43 @@ def density(f):
 
 def velocity(f, rho, force):
     """u from rho u = sum_i f_i c_i + F dt/2 (eq. momentum), dt = 1."""
+    vs = velocity_set(f.shape[0])
     nd = f.ndim - 1
     u = np.empty((3,) + f.shape[1:])
     for a in range(3):
-        u[a] = ((f * _bc(C[:, a].astype(np.float64), nd)).sum(axis=0) + 0.5 * force[a]) / rho
+        u[a] = ((f * _bc(vs.C[:, a].astype(np.float64), nd)).sum(axis=0) + 0.5 * force[a]) / rho
     return u
 
 
-def equilibrium(rho, u):
-    """Second-order equilibrium f_eq_i(rho, u) (eq. local_eq), shape (19, ...)."""
+def equilibrium(rho, u, q=19):
+    """Second-order equilibrium f_eq_i(rho, u) (eq. local_eq), shape (q, ...)."""
+    vs = velocity_set(q)
     nd = rho.ndim
-    cu = np.einsum("ia,a...->i...", C.astype(np.float64), u)
+    cu = np.einsum("ia,a...->i...", vs.C.astype(np.float64), u)
     uu = (u * u).sum(axis=0)
-    return _bc(W, nd) * rho[None] * (1.0 + cu / CS2 + cu ** 2 / (2.0 * CS4) - uu[None] / (2.0 * CS2))
+    return _bc(vs.W, nd) * rho[None] * (1.0 + cu / CS2 + cu ** 2 / (2.0 * CS4) - uu[None] / (2.0 * CS2))
 
 
 def second_moment(h):
     """sum_i c_i c_i h_i as a (3, 3, ...) tensor (eq. tensor)."""
-    return np.einsum("ia,ib,i...->ab...", C.astype(np.float64), C.astype(np.float64), h)
+    Cf = velocity_set(h.shape[0]).C.astype(np.float64)
+    return np.einsum("ia,ib,i...->ab...", Cf, Cf, h)
 
 
-def hermite_part(pi_neq):
+def hermite_part(pi_neq, q=19):
     """w_i/(2 c_s^4) Q_i : Pi_neq (eq. f_i_neq with the factor 1/2, see header)."""
+    vs = velocity_set(q)
     nd = pi_neq.ndim - 2
-    qp = np.einsum("iab,ab...->i...", QT, pi_neq)
-    return _bc(W, nd) / (2.0 * CS4) * qp
+    qp = np.einsum("iab,ab...->i...", vs.QT, pi_neq)
+    return _bc(vs.W, nd) / (2.0 * CS4) * qp
 
 
-def first_order_part(j_neq):
+def first_order_part(j_neq, q=19):
     """w_i c_i . J_neq / c_s^2: first-order Hermite projection of a non-equilibrium part."""
+    vs = velocity_set(q)
     nd = j_neq.ndim - 1
-    cj = np.einsum("ia,a...->i...", C.astype(np.float64), j_neq)
-    return _bc(W, nd) * cj / CS2
+    cj = np.einsum("ia,a...->i...", vs.C.astype(np.float64), j_neq)
+    return _bc(vs.W, nd) * cj / CS2
 
 
 def q_half(pi_neq):
@@ -142,30 +178,34 @@ def sponge_factor(nx, sponge_cells, K, p):
     return fac
 
 
-def guo_source(u, tau, force):
-    """Guo forcing F_i (eq. bodyforce) for acceleration F, shape (19, ...)."""
+def guo_source(u, tau, force, q=19):
+    """Guo forcing F_i (eq. bodyforce) for acceleration F, shape (q, ...)."""
+    vs = velocity_set(q)
     nd = u.ndim - 1
-    Cf = C.astype(np.float64)
-    out = np.zeros((Q,) + u.shape[1:])
+    Cf = vs.C.astype(np.float64)
+    out = np.zeros((vs.Q,) + u.shape[1:])
     cu = np.einsum("ia,a...->i...", Cf, u)
     for a in range(3):
         if force[a] == 0.0:
             continue
         term = (_bc(Cf[:, a], nd) - u[a][None]) / CS2 + cu / CS4 * _bc(Cf[:, a], nd)
         out += term * force[a]
-    return (1.0 - 1.0 / (2.0 * tau))[None] * _bc(W, nd) * out
+    return (1.0 - 1.0 / (2.0 * tau))[None] * _bc(vs.W, nd) * out
 
 
 def collide(f, tau0, cs_smag, force, sponge, operator="regularized"):
-    """Regularized BGK collision with Smagorinsky tau_eff, sponge and Guo force.
+    """BGK-type collision with Smagorinsky tau_eff, sponge and Guo force.
 
-    f: post-streaming populations (after any boundary rebuild), (19, NZ, NY, NX).
-    sponge: (NX,) viscosity multipliers.  Returns (f_post, rho, u).
-    operator="bgk" relaxes the full f - f_eq instead (oracle-only self-test).
+    f: post-streaming populations (after any boundary rebuild), (Q, NZ, NY, NX)
+    for any of the velocity sets.  sponge: (NX,) viscosity multipliers.
+    operator="regularized" relaxes the Hermite projection of f - f_eq (orders 1
+    and 2, see header); operator="bgk" relaxes the full f - f_eq (eq. lbe, the
+    paper's plain BGK bulk).  Returns (f_post, rho, u).
     """
+    q = f.shape[0]
     rho = density(f)
     u = velocity(f, rho, force)
-    feq = equilibrium(rho, u)
+    feq = equilibrium(rho, u, q)
     fneq = f - feq
     pi_neq = second_moment(fneq)
     tau = tau_effective(tau0, cs_smag, q_half(pi_neq), rho)
@@ -173,11 +213,11 @@ def collide(f, tau0, cs_smag, force, sponge, operator="regularized"):
     if operator == "bgk":
         reg = fneq
     else:
-        j_neq = np.einsum("ia,i...->a...", C.astype(np.float64), fneq)
-        reg = first_order_part(j_neq) + hermite_part(pi_neq)
+        j_neq = np.einsum("ia,i...->a...", velocity_set(q).C.astype(np.float64), fneq)
+        reg = first_order_part(j_neq, q) + hermite_part(pi_neq, q)
     f_post = feq + (1.0 - 1.0 / tau)[None] * reg
     if any(fc != 0.0 for fc in force):
-        f_post = f_post + guo_source(u, tau, force)
+        f_post = f_post + guo_source(u, tau, force, q)
     return f_post, rho, u
 
 
@@ -191,17 +231,18 @@ def stream(f_post, periodic_x, periodic_y=False):
     use of them before the boundary rebuild shows up.  periodic_y replaces the
     walls by wrap-around (oracle-only, for the shear-wave self-test).
     """
+    vs = velocity_set(f_post.shape[0])
     _, nz, ny, nx = f_post.shape
     ft = np.empty_like(f_post)
-    for i in range(Q):
-        cx, cy, cz = (int(v) for v in C[i])
+    for i in range(vs.Q):
+        cx, cy, cz = (int(v) for v in vs.C[i])
         ft[i] = np.roll(f_post[i], shift=(cz, cy, cx), axis=(0, 1, 2))
         if periodic_y:
             pass
         elif cy == 1:
-            ft[i][:, 0, :] = f_post[OPP[i]][:, 0, :]
+            ft[i][:, 0, :] = f_post[vs.OPP[i]][:, 0, :]
         elif cy == -1:
-            ft[i][:, ny - 1, :] = f_post[OPP[i]][:, ny - 1, :]
+            ft[i][:, ny - 1, :] = f_post[vs.OPP[i]][:, ny - 1, :]
         if not periodic_x:
             if cx == 1:
                 ft[i][:, :, 0] = np.nan
@@ -220,13 +261,14 @@ def regularized_rebuild(f_plane, rho_bc, u_bc, unknown):
     the unknown set (eq. unknown_neq), Pi_neq = sum_i Q_i f_neq_i (eq. pi_neq),
     f_i = f_eq_i + w_i/(2 c_s^4) Q_i:Pi_neq for every i.
     """
-    feq = equilibrium(rho_bc, u_bc)
+    vs = velocity_set(f_plane.shape[0])
+    feq = equilibrium(rho_bc, u_bc, vs.Q)
     fneq = f_plane - feq
-    for i in range(Q):
+    for i in range(vs.Q):
         if unknown[i]:
-            fneq[i] = fneq[OPP[i]]
-    pi_neq = np.einsum("iab,i...->ab...", QT, fneq)
-    return feq + hermite_part(pi_neq)
+            fneq[i] = fneq[vs.OPP[i]]
+    pi_neq = np.einsum("iab,i...->ab...", vs.QT, fneq)
+    return feq + hermite_part(pi_neq, vs.Q)
 
 
 def inlet_density(f_plane, u_bc_x):
@@ -234,8 +276,9 @@ def inlet_density(f_plane, u_bc_x):
 
     rho_bc = (sum_{c_x = 0} f + 2 sum_{c_x = -1} f) / (1 + u.n), u.n = -u_x.
     """
-    tang = f_plane[C[:, 0] == 0].sum(axis=0)
-    toward = f_plane[C[:, 0] == -1].sum(axis=0)
+    Cs = velocity_set(f_plane.shape[0]).C
+    tang = f_plane[Cs[:, 0] == 0].sum(axis=0)
+    toward = f_plane[Cs[:, 0] == -1].sum(axis=0)
     return (2.0 * toward + tang) / (1.0 - u_bc_x)
 
 
@@ -245,23 +288,24 @@ def outlet_velocity(f_plane, rho_out):
     rho_out (1 + u_x) = sum_{c_x = 0} f + 2 sum_{c_x = +1} f; tangential
     velocity zero (reading of the regularized pressure outlet).
     """
-    tang = f_plane[C[:, 0] == 0].sum(axis=0)
-    toward = f_plane[C[:, 0] == 1].sum(axis=0)
+    Cs = velocity_set(f_plane.shape[0]).C
+    tang = f_plane[Cs[:, 0] == 0].sum(axis=0)
+    toward = f_plane[Cs[:, 0] == 1].sum(axis=0)
     ux = (tang + 2.0 * toward) / rho_out - 1.0
     u = np.zeros((3,) + ux.shape)
     u[0] = ux
     return u
 
 
-INLET_UNKNOWN = C[:, 0] == 1
-OUTLET_UNKNOWN = C[:, 0] == -1
+INLET_UNKNOWN = D3Q19.INLET_UNKNOWN
+OUTLET_UNKNOWN = D3Q19.OUTLET_UNKNOWN
 
 
 def apply_inlet(ft, u_bc_zy):
     """Rebuild the x = 0 plane from the inlet velocity u_bc (3, NZ, NY)."""
     plane = ft[:, :, :, 0]
     rho_bc = inlet_density(plane, u_bc_zy[0])
-    ft[:, :, :, 0] = regularized_rebuild(plane, rho_bc, u_bc_zy, INLET_UNKNOWN)
+    ft[:, :, :, 0] = regularized_rebuild(plane, rho_bc, u_bc_zy, velocity_set(ft.shape[0]).INLET_UNKNOWN)
 
 
 def apply_outlet(ft, rho_out):
@@ -269,7 +313,7 @@ def apply_outlet(ft, rho_out):
     plane = ft[:, :, :, -1]
     u = outlet_velocity(plane, rho_out)
     rho = np.full(plane.shape[1:], float(rho_out))
-    ft[:, :, :, -1] = regularized_rebuild(plane, rho, u, OUTLET_UNKNOWN)
+    ft[:, :, :, -1] = regularized_rebuild(plane, rho, u, velocity_set(ft.shape[0]).OUTLET_UNKNOWN)
 
 
 def lattice_step(f_post, *, tau0, cs_smag, force, sponge, periodic_x, u_bc_zy=None, rho_out=1.0,
