@@ -22,9 +22,10 @@
  * Distributions.  Stored as deviations g_i = f_i - w_i in two buffers
  * (read one, write the other, swapped every step), as FP32, FP16 or BF16
  * (round to nearest even); arithmetic is FP32, statistics FP64.
- * Device layout [NZ][19][NY][NX] (each z slice holds all 19 populations,
+ * Device layout [NZ][Q][NY][NX] (each z slice holds all Q populations, Q = 19
+ * unless the descriptor selects D3Q15 or D3Q27;
  * x fastest); the host-side arrays of get_f/set_f/get_f_planes are
- * [19][NZ][NY][NX].  Population order: rest;
+ * [Q][NZ][NY][NX].  D3Q19 population order: rest;
  * +x, -x, +y, -y, +z, -z; (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0),
  * (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1),
  * (0,-1,1).
@@ -69,6 +70,15 @@ typedef struct {
   int32_t sponge_cells;     /* L_s: sponge over x in [NX-1-L_s, NX-1]; 0 = off        */
   int32_t max_modes;        /* capacity of the STG mode tables (0 if periodic_x)      */
   int32_t max_rans;         /* capacity of the RANS input staging (0 if periodic_x)   */
+  int32_t velocity_set;     /* 19 (or 0): D3Q19, the method's set; 15: D3Q15; 27:
+                               D3Q27 (the boundary treatment carries over, Numerical
+                               method).  Population order: rest, then opposite pairs
+                               (i, i+1), i odd: the 6 axes, then for D3Q19/D3Q27 the
+                               12 face diagonals, then for D3Q15/D3Q27 the 8 corners
+                               (1,1,1), (-1,-1,-1), (1,1,-1), (-1,-1,1), (1,-1,1),
+                               (-1,1,-1), (-1,1,1), (1,-1,-1)                          */
+  int32_t collision;        /* 0: regularized BGK bulk (the default configuration);
+                               1: plain BGK bulk, eq. lbe                              */
   double nu_lb;             /* molecular viscosity; tau0 = 1/2 + 3 nu (eq. lbe-nu)    */
   double cs_smag;           /* Smagorinsky Cs; the paper's C = Cs^2 (eq. smogrinsky)  */
   double force[3];          /* Guo volume acceleration (eq. bodyforce)               */
@@ -156,14 +166,14 @@ int stglbm_stats_stop(stglbm_t h);
  * the number of sampled steps.  Synchronizes. n = NX*NY*9. */
 int stglbm_get_stats(stglbm_t h, double* h_out, uint64_t n, int64_t* n_samples);
 
-/* Current distributions f = w + g as FP64 [19][NZ][NY][NX]; synchronizes.
- * Uses the inactive buffer as staging. n = 19*NX*NY*NZ. */
+/* Current distributions f = w + g as FP64 [Q][NZ][NY][NX]; synchronizes.
+ * Uses the inactive buffer as staging. n = Q*NX*NY*NZ. */
 int stglbm_get_f(stglbm_t h, double* h_out, uint64_t n);
-/* f = w + g for the planes x0 <= x < x1 only, FP64 [19][NZ][NY][x1-x0];
- * synchronizes. n = 19*NZ*NY*(x1-x0). */
+/* f = w + g for the planes x0 <= x < x1 only, FP64 [Q][NZ][NY][x1-x0];
+ * synchronizes. n = Q*NZ*NY*(x1-x0). */
 int stglbm_get_f_planes(stglbm_t h, int32_t x0, int32_t x1, double* h_out, uint64_t n);
 /* Device address and size in bytes of the current distributions g (store
- * type, device layout [NZ][19][NY][NX]); valid until the next step or
+ * type, device layout [NZ][Q][NY][NX]); valid until the next step or
  * restore. */
 int stglbm_state_view(stglbm_t h, void** d_g, uint64_t* bytes);
 /* Replace the distributions by f (rounded to the store type). Synchronizes. */

@@ -20,6 +20,7 @@ E_REALIZABILITY = -6
 
 F32, F16, BF16 = 0, 1, 2
 STORES = {"f32": F32, "f16": F16, "bf16": BF16}
+COLLISIONS = {"regularized": 0, "bgk": 1}
 ROW_FIELDS = 18
 
 c_int32, c_int64, c_uint64, c_double = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
@@ -31,6 +32,7 @@ class LatticeDesc(ctypes.Structure):
     _fields_ = [
         ("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("store", c_int32),
         ("periodic_x", c_int32), ("sponge_cells", c_int32), ("max_modes", c_int32), ("max_rans", c_int32),
+        ("velocity_set", c_int32), ("collision", c_int32),
         ("nu_lb", c_double), ("cs_smag", c_double), ("force", c_double * 3), ("rho_out", c_double),
         ("sponge_K", c_double), ("sponge_p", c_double),
     ]

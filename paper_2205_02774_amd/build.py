@@ -7,30 +7,45 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libstglbm.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("lattice_kernels.hip", "inlet_kernels.hip", "api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in
+           ("lattice_kernels.hip", "lattice_variants.hip", "inlet_kernels.hip", "api.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
+    "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
 ]
+NOISE = "packed-fp32-ops"
+
+
+def _run(cmd):
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if NOISE not in l)
+    return res.returncode, msgs
 
 
 def build(verbose=False):
-    """Compile every HIP source into the shared library next to this file."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           *SOURCES, "-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    noise = "packed-fp32-ops"
-    msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if noise not in l)
-    if res.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({res.returncode}):\n{msgs}")
-    if verbose and msgs.strip():
-        print(msgs, flush=True)
+    """Compile every HIP source (in parallel) and link the shared library next to this file."""
+    import concurrent.futures
+    import tempfile
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    with tempfile.TemporaryDirectory(prefix="stglbm_build_") as tmpdir:
+        objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in SOURCES]
+        cmds = [[HIPCC, *FLAGS, *inc, "-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+        with concurrent.futures.ThreadPoolExecutor(max_workers=len(cmds)) as pool:
+            results = list(pool.map(_run, cmds))
+        for cmd, (rc, msgs) in zip(cmds, results):
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            if rc != 0:
+                raise RuntimeError(f"hipcc failed ({rc}) on {cmd[-3]}:\n{msgs}")
+            if verbose and msgs.strip():
+                print(msgs, flush=True)
+        tmp = LIB + ".tmp"
+        rc, msgs = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
+        if rc != 0:
+            raise RuntimeError(f"link failed ({rc}):\n{msgs}")
     os.replace(tmp, LIB)
     return LIB
 

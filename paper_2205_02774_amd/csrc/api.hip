@@ -21,7 +21,7 @@ namespace {
 constexpr int kVersion = 10000;        // 1.0.0
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kCkptMagic = 0x5354474cu;   // "STGL"
-constexpr uint32_t kCkptVersion = 2;   // 2: store order [NZ][19][NY][NX]
+constexpr uint32_t kCkptVersion = 3;   // 2: store order [NZ][Q][NY][NX]; 3: velocity set and operator
 
 thread_local std::string g_lib_error;
 
@@ -35,10 +35,13 @@ uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 int store_bytes(int store) { return store == STGLBM_F32 ? 4 : 2; }
 
+// Populations of the descriptor's velocity set (0 selects D3Q19).
+int set_size(const stglbm_lattice_desc* d) { return d->velocity_set == 0 ? 19 : d->velocity_set; }
+
 // The step kernel addresses one z slice of the store ([19][NY][NX] values)
 // through a raw buffer resource of at most 4 GiB - 1.
 bool slice_fits(const stglbm_lattice_desc* d) {
-  return static_cast<uint64_t>(kQ) * d->nx * d->ny * store_bytes(d->store) <= 0xffffffffull;
+  return static_cast<uint64_t>(set_size(d)) * d->nx * d->ny * store_bytes(d->store) <= 0xffffffffull;
 }
 
 const char* check_desc(const stglbm_lattice_desc* d) {
@@ -46,7 +49,10 @@ const char* check_desc(const stglbm_lattice_desc* d) {
   if (d->nx < 2 || d->ny < 2 || d->nz < 1) return "lattice must have nx >= 2, ny >= 2, nz >= 1";
   if (static_cast<long long>(d->nx) * d->ny * d->nz > 0x7fffffffLL) return "lattice has 2^31 cells or more";
   if (d->store < 0 || d->store > 2) return "unknown store type";
-  if (!slice_fits(d)) return "lattice too large: one z slice (19 NY NX values) must stay below 4 GiB";
+  if (d->velocity_set != 0 && d->velocity_set != 15 && d->velocity_set != 19 && d->velocity_set != 27)
+    return "velocity_set must be 15, 19 or 27 (0 = 19)";
+  if (d->collision != 0 && d->collision != 1) return "collision must be 0 (regularized) or 1 (BGK)";
+  if (!slice_fits(d)) return "lattice too large: one z slice (Q NY NX values) must stay below 4 GiB";
   if (!(d->nu_lb > 0.0) || !std::isfinite(d->nu_lb)) return "nu_lb must be positive";
   if (!(d->cs_smag >= 0.0)) return "cs_smag must be >= 0";
   if (!d->periodic_x) {
@@ -83,6 +89,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
       if (n >= 5) interleave = il ? 1 : 0;
     }
   }
+  if (set_size(d) != 19 || d->collision != 0) vec = 1;   // the variants are built for one cell per lane
   L.vec = vec;
   L.nxt = (d->nx + 64 * vec - 1) / (64 * vec);
   if (wx == 0) wx = L.nxt < 8 ? L.nxt : 8;
@@ -107,7 +114,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
     off = align_up(off + bytes);
     return at;
   };
-  const uint64_t gbytes = static_cast<uint64_t>(kQ) * cells * store_bytes(d->store);
+  const uint64_t gbytes = static_cast<uint64_t>(set_size(d)) * cells * store_bytes(d->store);
   L.g[0] = take(gbytes);
   L.g[1] = take(gbytes);
   L.stats = take(static_cast<uint64_t>(L.slots) * 9 * d->nx * d->ny * sizeof(double));
@@ -143,6 +150,7 @@ struct CkptHeader {
   int64_t t, n_samples;
   int32_t sampling, n_modes;
   uint64_t g_bytes, stats_bytes;
+  int32_t q, collision;
 };
 
 }  // namespace
@@ -172,7 +180,8 @@ struct stglbm_ctx {
   template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
   void* gbuf(int k) { return ws + L.g[k]; }
   uint64_t cells() const { return static_cast<uint64_t>(d.nx) * d.ny * d.nz; }
-  uint64_t gbytes() const { return static_cast<uint64_t>(kQ) * cells() * store_bytes(d.store); }
+  int q() const { return set_size(&d); }
+  uint64_t gbytes() const { return static_cast<uint64_t>(q()) * cells() * store_bytes(d.store); }
 };
 
 namespace {
@@ -218,6 +227,8 @@ StepParams step_params(stglbm_t h) {
   p.gout = h->gbuf(1 - h->cur);
   p.plane2d = static_cast<long long>(d.nx) * d.ny;
   p.nx = d.nx; p.ny = d.ny; p.nz = d.nz;
+  p.q = h->q();
+  p.collision = d.collision;
   p.vec = h->L.vec;
   p.nxt = h->L.nxt; p.wx = h->L.wx; p.wz = h->L.wz; p.nxg = h->L.nxg;
   p.slots = h->L.slots; p.lw = h->L.lw; p.zstep = h->L.zstep; p.nblocks = h->L.nblocks;
@@ -433,6 +444,7 @@ int stglbm_step(stglbm_t h, int32_t n_steps) {
       ProbeParams q{};
       q.g = h->gbuf(h->cur);
       q.plane2d = static_cast<long long>(h->d.nx) * h->d.ny;
+      q.q = h->q();
       q.nx = h->d.nx;
       q.n = h->n_probes;
       q.fx = h->d.force[0];
@@ -513,14 +525,14 @@ int stglbm_get_stats(stglbm_t h, double* h_out, uint64_t n, int64_t* n_samples) 
 
 int stglbm_get_f(stglbm_t h, double* h_out, uint64_t n) {
   if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
-  const uint64_t total = static_cast<uint64_t>(kQ) * h->cells();
-  if (!h_out || n != total) return fail(h, STGLBM_E_INVAL, "f buffer must hold 19*NX*NY*NZ doubles");
+  const uint64_t total = static_cast<uint64_t>(h->q()) * h->cells();
+  if (!h_out || n != total) return fail(h, STGLBM_E_INVAL, "f buffer must hold Q*NX*NY*NZ doubles");
   const int rc = sync_and_check(h);
   double* stage = static_cast<double*>(h->gbuf(1 - h->cur));
   const uint64_t chunk = h->gbytes() / sizeof(double);
   for (uint64_t off = 0; off < total; off += chunk) {
     const uint64_t cnt = std::min<uint64_t>(chunk, total - off);
-    HIP_CHECK(h, launch_export_f(h->gbuf(h->cur), h->d.store, off, cnt, h->d.nz,
+    HIP_CHECK(h, launch_export_f(h->gbuf(h->cur), h->d.store, h->q(), off, cnt, h->d.nz,
                                  static_cast<long long>(h->d.nx) * h->d.ny, stage, h->stream), "export kernel");
     HIP_CHECK(h, hipMemcpyAsync(h_out + off, stage, cnt * sizeof(double), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync f");
     HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
@@ -531,12 +543,12 @@ int stglbm_get_f(stglbm_t h, double* h_out, uint64_t n) {
 int stglbm_get_f_planes(stglbm_t h, int32_t x0, int32_t x1, double* h_out, uint64_t n) {
   if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
   if (x0 < 0 || x1 > h->d.nx || x1 <= x0) return fail(h, STGLBM_E_INVAL, "need 0 <= x0 < x1 <= NX");
-  const uint64_t total = static_cast<uint64_t>(kQ) * h->d.nz * h->d.ny * (x1 - x0);
-  if (!h_out || n != total) return fail(h, STGLBM_E_INVAL, "buffer must hold 19*NZ*NY*(x1-x0) doubles");
+  const uint64_t total = static_cast<uint64_t>(h->q()) * h->d.nz * h->d.ny * (x1 - x0);
+  if (!h_out || n != total) return fail(h, STGLBM_E_INVAL, "buffer must hold Q*NZ*NY*(x1-x0) doubles");
   if (total * sizeof(double) > h->gbytes()) return fail(h, STGLBM_E_INVAL, "plane range larger than the staging buffer");
   const int rc = sync_and_check(h);
   double* stage = static_cast<double*>(h->gbuf(1 - h->cur));
-  HIP_CHECK(h, launch_export_planes(h->gbuf(h->cur), h->d.store, h->d.nx, h->d.ny, h->d.nz, x0, x1, stage, h->stream),
+  HIP_CHECK(h, launch_export_planes(h->gbuf(h->cur), h->d.store, h->q(), h->d.nx, h->d.ny, h->d.nz, x0, x1, stage, h->stream),
             "export kernel");
   HIP_CHECK(h, hipMemcpyAsync(h_out, stage, total * sizeof(double), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync f");
   HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
@@ -552,8 +564,8 @@ int stglbm_state_view(stglbm_t h, void** d_g, uint64_t* bytes) {
 
 int stglbm_set_f(stglbm_t h, const double* h_in, uint64_t n) {
   if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
-  const uint64_t total = static_cast<uint64_t>(kQ) * h->cells();
-  if (!h_in || n != total) return fail(h, STGLBM_E_INVAL, "f buffer must hold 19*NX*NY*NZ doubles");
+  const uint64_t total = static_cast<uint64_t>(h->q()) * h->cells();
+  if (!h_in || n != total) return fail(h, STGLBM_E_INVAL, "f buffer must hold Q*NX*NY*NZ doubles");
   const int rc = sync_and_check(h);
   if (rc != STGLBM_OK && rc != STGLBM_E_UNSTABLE) return rc;
   double* stage = static_cast<double*>(h->gbuf(1 - h->cur));
@@ -561,7 +573,7 @@ int stglbm_set_f(stglbm_t h, const double* h_in, uint64_t n) {
   for (uint64_t off = 0; off < total; off += chunk) {
     const uint64_t cnt = std::min<uint64_t>(chunk, total - off);
     HIP_CHECK(h, hipMemcpyAsync(stage, h_in + off, cnt * sizeof(double), hipMemcpyHostToDevice, h->stream), "hipMemcpyAsync f");
-    HIP_CHECK(h, launch_import_f(stage, h->d.store, off, cnt, h->d.nz,
+    HIP_CHECK(h, launch_import_f(stage, h->d.store, h->q(), off, cnt, h->d.nz,
                                  static_cast<long long>(h->d.nx) * h->d.ny, h->gbuf(h->cur), h->stream), "import kernel");
     HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   }
@@ -576,10 +588,10 @@ int stglbm_set_equilibrium(stglbm_t h, const double* h_u, uint64_t n) {
   if (!h_u || n != total) return fail(h, STGLBM_E_INVAL, "u buffer must hold 3*NX*NY*NZ doubles");
   const int rc = sync_and_check(h);
   if (rc != STGLBM_OK && rc != STGLBM_E_UNSTABLE) return rc;
-  // staged in the idle distribution buffer (19 s >= 24 bytes per cell for every store type)
+  // staged in the idle distribution buffer (Q s >= 30 >= 24 bytes per cell for every set and store)
   double* stage = static_cast<double*>(h->gbuf(1 - h->cur));
   HIP_CHECK(h, hipMemcpyAsync(stage, h_u, total * sizeof(double), hipMemcpyHostToDevice, h->stream), "hipMemcpyAsync u");
-  HIP_CHECK(h, launch_equilibrium(stage, h->d.store, h->d.nx, h->d.ny, h->d.nz, h->gbuf(h->cur), h->stream),
+  HIP_CHECK(h, launch_equilibrium(stage, h->d.store, h->q(), h->d.nx, h->d.ny, h->d.nz, h->gbuf(h->cur), h->stream),
             "equilibrium kernel");
   HIP_CHECK(h, launch_fill_zero(h->at<char>(h->L.flag), kAlign, h->stream), "flag reset");
   HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
@@ -656,6 +668,7 @@ int stglbm_checkpoint(stglbm_t h, void* h_buf, uint64_t n) {
   hd.slots = h->L.slots; hd.inlet_hash = h->inlet_hash; hd.t = h->t; hd.n_samples = h->n_samples;
   hd.sampling = h->sampling ? 1 : 0; hd.n_modes = h->n_modes;
   hd.g_bytes = h->gbytes(); hd.stats_bytes = h->L.sponge - h->L.stats;
+  hd.q = h->q(); hd.collision = h->d.collision;
   char* out = static_cast<char*>(h_buf);
   std::memcpy(out, &hd, sizeof(hd));
   HIP_CHECK(h, hipMemcpy(out + sizeof(hd), h->gbuf(h->cur), hd.g_bytes, hipMemcpyDeviceToHost), "hipMemcpy g");
@@ -670,7 +683,8 @@ int stglbm_restore(stglbm_t h, const void* h_buf, uint64_t n) {
   std::memcpy(&hd, h_buf, sizeof(hd));
   if (hd.magic != kCkptMagic || hd.version != kCkptVersion) return fail(h, STGLBM_E_INVAL, "not a checkpoint of this library");
   if (hd.nx != h->d.nx || hd.ny != h->d.ny || hd.nz != h->d.nz || hd.store != h->d.store ||
-      hd.periodic_x != h->d.periodic_x || hd.slots != h->L.slots)
+      hd.periodic_x != h->d.periodic_x || hd.slots != h->L.slots || hd.q != h->q() ||
+      hd.collision != h->d.collision)
     return fail(h, STGLBM_E_INVAL, "checkpoint lattice differs from the handle's");
   if (!h->d.periodic_x && (!h->inlet_ready || hd.inlet_hash != h->inlet_hash || hd.n_modes != h->n_modes))
     return fail(h, STGLBM_E_STATE, "install the same inlet (set_rans_inlet) before restoring");

@@ -6,7 +6,6 @@
 
 namespace stglbm {
 
-constexpr int kQ = 19;
 constexpr int kRowFields = 18;      // U(3) k omega R(6) a(6) l_e
 constexpr int kModeFields = 8;      // k, d(3), sigma(3), phi
 constexpr int kScalars = 8;         // L_e k_min k_max alpha k_cut clamps U_b N
@@ -20,10 +19,12 @@ constexpr int kFlagInletMach = 2;   // |u_bc,x| >= 0.3 c_s at an inlet node
 
 // Fused stream-collide pass, one launch per time step.
 struct StepParams {
-  const void* gin;          // g at step n, [NZ][19][NY][NX] in the store type
+  const void* gin;          // g at step n, [NZ][Q][NY][NX] in the store type
   void* gout;               // g at step n+1
   long long plane2d;        // NX*NY: one population of one z slice
   int nx, ny, nz;
+  int q;                    // velocity set: 15, 19 or 27 populations
+  int collision;            // 0 regularized, 1 plain BGK
   int vec;                  // consecutive x cells per lane (1, 2 or 4)
   int nxt;                  // number of x tiles of 64 * vec cells
   int wx, wz;               // block = wx waves along x times wz waves along z
@@ -50,9 +51,9 @@ struct StepParams {
 // Velocity probes: after a step, u at up to kMaxProbes cells of the new state.
 constexpr int kMaxProbes = 64;
 struct ProbeParams {
-  const void* g;            // state just written, [NZ][19][NY][NX]
+  const void* g;            // state just written, [NZ][Q][NY][NX]
   long long plane2d;        // NX*NY
-  int nx, n;
+  int q, nx, n;
   double fx, fy, fz;        // Guo acceleration (u = (sum c f - F/2) / rho)
   int xyz[kMaxProbes][3];
   float* out;               // this step's row of the series: [n][3]
@@ -90,18 +91,19 @@ struct SetupParams {
 };
 
 hipError_t launch_step(const StepParams& p, int store, bool stats, hipStream_t s);
+hipError_t launch_step_variant(const StepParams& p, int store, bool stats, hipStream_t s);
 hipError_t launch_stg(const StgParams& p, hipStream_t s);
 hipError_t launch_inlet_setup(const SetupParams& p, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, unsigned long long bytes, hipStream_t s);
 hipError_t launch_sponge(float* sponge, int nx, int cells, double K, double p, hipStream_t s);
-// Public order [19][NZ][NY][NX] <-> stored order [NZ][19][NY][NX].
-hipError_t launch_export_f(const void* g, int store, long long offset, long long count, int nz,
+// Public order [Q][NZ][NY][NX] <-> stored order [NZ][Q][NY][NX].
+hipError_t launch_export_f(const void* g, int store, int q, long long offset, long long count, int nz,
                            long long plane2d, double* out, hipStream_t s);
-hipError_t launch_export_planes(const void* g, int store, int nx, int ny, int nz, int x0, int x1,
-                               double* out, hipStream_t s);
-hipError_t launch_import_f(const double* f, int store, long long offset, long long count, int nz,
+hipError_t launch_export_planes(const void* g, int store, int q, int nx, int ny, int nz, int x0, int x1,
+                                double* out, hipStream_t s);
+hipError_t launch_import_f(const double* f, int store, int q, long long offset, long long count, int nz,
                            long long plane2d, void* g, hipStream_t s);
-hipError_t launch_equilibrium(const double* u, int store, int nx, int ny, int nz, void* g, hipStream_t s);
+hipError_t launch_equilibrium(const double* u, int store, int q, int nx, int ny, int nz, void* g, hipStream_t s);
 hipError_t launch_probes(const ProbeParams& p, int store, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, unsigned long long bytes, hipStream_t s);
 

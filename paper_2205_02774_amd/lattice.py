@@ -27,7 +27,8 @@ def derive_units(delta, ny, u_b_lb, U_b, nu_phys):
 
 
 def make_desc(nx, ny, nz, *, nu_lb, store="f32", periodic_x=False, cs_smag=0.1, force=(0.0, 0.0, 0.0),
-              rho_out=1.0, sponge_cells=0, sponge_K=1000.0, sponge_p=3.0, max_modes=0, max_rans=0):
+              rho_out=1.0, sponge_cells=0, sponge_K=1000.0, sponge_p=3.0, max_modes=0, max_rans=0,
+              velocity_set=19, collision="regularized"):
     d = abi.LatticeDesc()
     d.nx, d.ny, d.nz = nx, ny, nz
     d.store = abi.STORES[store] if isinstance(store, str) else int(store)
@@ -39,6 +40,8 @@ def make_desc(nx, ny, nz, *, nu_lb, store="f32", periodic_x=False, cs_smag=0.1, 
     for a in range(3):
         d.force[a] = float(force[a])
     d.rho_out, d.sponge_K, d.sponge_p = float(rho_out), float(sponge_K), float(sponge_p)
+    d.velocity_set = int(velocity_set)
+    d.collision = abi.COLLISIONS[collision] if isinstance(collision, str) else int(collision)
     return d
 
 
@@ -56,6 +59,7 @@ class Lattice:
         self.lib = abi.load()
         self.desc = make_desc(nx, ny, nz, **desc_kw)
         self.nx, self.ny, self.nz = nx, ny, nz
+        self.q = self.desc.velocity_set or 19
         self.device = torch.device(device)
         self.nbytes = footprint(self.desc)
         self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
@@ -131,19 +135,19 @@ class Lattice:
         return out, ns.value
 
     def get_f(self):
-        out = np.empty((19, self.nz, self.ny, self.nx))
+        out = np.empty((self.q, self.nz, self.ny, self.nx))
         self._chk(self.lib.stglbm_get_f(self.handle, _dptr(out), out.size))
         return out
 
     def get_f_planes(self, x0, x1):
-        out = np.empty((19, self.nz, self.ny, x1 - x0))
+        out = np.empty((self.q, self.nz, self.ny, x1 - x0))
         self._chk(self.lib.stglbm_get_f_planes(self.handle, int(x0), int(x1), _dptr(out), out.size))
         return out
 
     def state_view(self):
-        """Torch view (19, NZ, NY, NX) of the current deviations g on the device.
+        """Torch view (Q, NZ, NY, NX) of the current deviations g on the device.
 
-        The device store is [NZ][19][NY][NX]; the view permutes it (no copy).
+        The device store is [NZ][Q][NY][NX]; the view permutes it (no copy).
         FP32 stores give float32; FP16/BF16 stores give float16/bfloat16.
         Valid until the next step or restore.
         """
@@ -152,12 +156,12 @@ class Lattice:
         off = ptr.value - self.workspace.data_ptr()
         dt = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}[self.desc.store]
         raw = self.workspace[off: off + nb.value]
-        return raw.view(dt).view(self.nz, 19, self.ny, self.nx).permute(1, 0, 2, 3)
+        return raw.view(dt).view(self.nz, self.q, self.ny, self.nx).permute(1, 0, 2, 3)
 
     def set_f(self, f):
         f = np.ascontiguousarray(f, dtype=np.float64)
-        if f.shape != (19, self.nz, self.ny, self.nx):
-            raise ValueError("f must have shape (19, NZ, NY, NX)")
+        if f.shape != (self.q, self.nz, self.ny, self.nx):
+            raise ValueError("f must have shape (Q, NZ, NY, NX)")
         self._chk(self.lib.stglbm_set_f(self.handle, _dptr(f), f.size))
 
     def set_equilibrium(self, u):
@@ -244,7 +248,8 @@ class Lattice:
         return {"step_ms": out[0], "step_launches": int(out[1]), "stg_ms": out[2], "stg_launches": int(out[3])}
 
 
-def channel_from_config(cfg, *, store=None, device="cuda", stream=None, periodic_x=False, max_modes=None):
+def channel_from_config(cfg, *, store=None, device="cuda", stream=None, periodic_x=False, max_modes=None,
+                        velocity_set=19, collision="regularized"):
     """Build an inlet/outlet channel from a configuration dictionary.
 
     cfg holds the lattice size, Re_tau-derived physical parameters and the
@@ -257,7 +262,8 @@ def channel_from_config(cfg, *, store=None, device="cuda", stream=None, periodic
                   store=store or cfg["store"], periodic_x=periodic_x, nu_lb=nu_lb, cs_smag=cfg["cs_smag"],
                   force=cfg["force"], rho_out=cfg["rho_out"], sponge_cells=cfg["sponge_cells"],
                   sponge_K=cfg["sponge_K"], sponge_p=cfg["sponge_p"],
-                  max_modes=max_modes or n_modes, max_rans=len(rans["y"]))
+                  max_modes=max_modes or n_modes, max_rans=len(rans["y"]), velocity_set=velocity_set,
+                  collision=collision)
     lat.c_x, lat.c_t, lat.nu_lb = c_x, c_t, nu_lb
     if not periodic_x:
         lat.set_rans_inlet(rans, delta=cfg["delta"], nu_phys=cfg["nu_phys"], c_x=c_x, c_t=c_t, U_b=rans["U_b"],

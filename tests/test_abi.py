@@ -94,3 +94,17 @@ def test_derive_units_matches_oracle(lib):
     got = derive_units(1.0, 128, 0.05, 15.37, 1 / 180)
     c_x, c_t, nu_lb, _ = units.channel_units(1.0, 128, 0.05, 15.37, 1 / 180)
     assert got == pytest.approx((c_x, c_t, nu_lb), rel=1e-15)
+
+
+def test_velocity_set_and_collision_validation(lib):
+    from paper_2205_02774_amd import abi, make_desc, footprint
+    base = footprint(make_desc(64, 32, 32, nu_lb=1e-3, periodic_x=True))
+    f27 = footprint(make_desc(64, 32, 32, nu_lb=1e-3, periodic_x=True, velocity_set=27))
+    f15 = footprint(make_desc(64, 32, 32, nu_lb=1e-3, periodic_x=True, velocity_set=15))
+    g19 = 2 * 19 * 64 * 32 * 32 * 4
+    assert f27 - base == pytest.approx(g19 * 8 / 19, abs=1024) and base - f15 == pytest.approx(g19 * 4 / 19, abs=1024)
+    assert footprint(make_desc(64, 32, 32, nu_lb=1e-3, periodic_x=True, velocity_set=0)) == base
+    for bad in (dict(velocity_set=21), dict(collision=2), dict(collision="bgk", velocity_set=13)):
+        with pytest.raises(abi.StglbmError) as e:
+            footprint(make_desc(64, 32, 32, nu_lb=1e-3, periodic_x=True, **bad))
+        assert e.value.code == abi.E_INVAL
