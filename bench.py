@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                       # MI355X HBM3E
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SRC = os.path.join(ROOT, "paper_2205_02774_amd", "csrc", "lattice_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2205_02774_amd", "csrc", f) for f in ("lattice_step.h", "lattice_kernels.hip")]
 
 
 def log(msg):
@@ -36,7 +36,11 @@ def log(msg):
 
 
 def kernel_hash():
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the sources of the stream-collide kernel (its header and the unit that instantiates it)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload, store):
@@ -50,14 +54,18 @@ def measured_traffic(workload, store):
     return rec.get("bytes_per_launch")
 
 
-def run_variant(cfg, store, steps, warmup, stats=True):
+def run_variant(cfg, store, steps, warmup, stats=True, velocity_set=19, collision="regularized"):
     import torch
     from paper_2205_02774_amd import channel_from_config
 
     t0 = time.perf_counter()
-    lat = channel_from_config(cfg, store=store, device="cuda:0")
-    lat.step(warmup)
-    lat.sync()
+    lat = channel_from_config(cfg, store=store, device="cuda:0", velocity_set=velocity_set, collision=collision)
+    try:
+        lat.step(warmup)
+        lat.sync()
+    except Exception:
+        lat.close()
+        raise
     log(f"[bench] {cfg['name']} {store}: setup + {warmup} warm-up steps in {time.perf_counter() - t0:.1f} s")
     if stats:
         lat.stats_reset()
@@ -73,7 +81,7 @@ def run_variant(cfg, store, steps, warmup, stats=True):
     st, ns = lat.get_stats()
     assert ns == (steps if stats else 0)
     cells = cfg["cells"]
-    bytes_per_cell = 2 * 19 * (4 if store == "f32" else 2)
+    bytes_per_cell = 2 * velocity_set * (4 if store == "f32" else 2)
     k_ms = prof["step_ms"] / prof["step_launches"]
     out = {
         "store": store,
@@ -85,7 +93,7 @@ def run_variant(cfg, store, steps, warmup, stats=True):
         "achieved_gbs": bytes_per_cell * cells / (k_ms * 1e-3) / 1e9,
         "mean_u_lb": float(st[..., 0].sum() / (ns * cells)),
     }
-    log(f"[bench] {store}: {out['ms_per_step']:.4f} ms/step, {out['mlups']:.0f} MLUPS, step kernel "
+    log(f"[bench] {store} D3Q{velocity_set} {collision}: {out['ms_per_step']:.4f} ms/step, {out['mlups']:.0f} MLUPS, step kernel "
         f"{k_ms:.4f} ms = {out['achieved_gbs']:.0f} GB/s, STG {out['stg_kernel_ms'] * 1e3:.1f} us")
     lat.close()
     del lat
@@ -270,6 +278,8 @@ def main():
     ap.add_argument("--workload", default="channel-512x128x256")
     ap.add_argument("--variants", default="f16,bf16", help="extra store types timed on the same workload")
     ap.add_argument("--variant-warmup", type=int, default=2000)
+    ap.add_argument("--lattice-variants", default="15:regularized,27:regularized,19:bgk",
+                    help="velocity-set:operator pairs timed (FP32) on the same workload ('' = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-scale", type=float, default=0.05,
                     help="step budgets of the 64-job serving mix are scaled by this (1.0 = full mix; 0 = skip)")
@@ -315,6 +325,22 @@ def main():
             "speedup_vs_f32": round(r["mlups"] / main_run["mlups"], 3),
             "warmup": args.variant_warmup,
         }
+    lattice_variants = {}
+    for spec in [v for v in args.lattice_variants.split(",") if v]:
+        q, op = spec.split(":")
+        try:
+            r = run_variant(cfg, "f32", args.steps, args.variant_warmup, velocity_set=int(q), collision=op)
+        except abi.StglbmError as e:            # e.g. plain BGK going unstable at tau0 - 1/2 = 3.4e-3
+            log(f"[bench] D3Q{q} {op}: {e}")
+            import torch
+            torch.cuda.empty_cache()
+            lattice_variants[f"D3Q{q}-{op}"] = {"status": "unstable", "message": str(e)}
+            continue
+        lattice_variants[f"D3Q{q}-{op}"] = {
+            "value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
+            "step_kernel_ms": round(r["step_kernel_ms"], 5), "algorithmic_bytes_per_cell": 2 * int(q) * 4,
+            "achieved_gbs": round(r["achieved_gbs"], 1), "roofline_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+            "warmup": args.variant_warmup}
     large = large_lattice(args.large, args.large_steps, args.large_warmup) if args.large else None
     periodic = periodic_reference(cfg["nx"], cfg["ny"], cfg["nz"], args.periodic_steps, 500) \
         if args.periodic_steps > 0 else None
@@ -356,6 +382,7 @@ def main():
             "stg_kernel_ms": round(main_run["stg_kernel_ms"], 5),
         },
         "variants": variants,
+        "lattice_variants": lattice_variants,
         "large": large,
         "periodic": periodic,
         "precision": precision,
