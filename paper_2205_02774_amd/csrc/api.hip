@@ -29,6 +29,8 @@ struct Layout {
   uint64_t g[2] = {0, 0}, stats = 0, sponge = 0, flag = 0, ubc = 0, rans = 0, rows = 0, modes = 0,
            sqrtq = 0, bz = 0, sig = 0, scalars = 0, total = 0;
   int vec = 1, nxt = 0, wx = 1, wz = 1, nxg = 0, slots = 0, lw = 0, zstep = 1, nblocks = 0;
+  bool short_chunks_when_idle = true;   // steps without statistics: lw_idle z rows per block
+  int lw_idle = 1;
 };
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -85,6 +87,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
     const int n = std::sscanf(env, "%d,%d,%d,%d,%d", &a, &b, &c, &v, &il);
     if (n >= 3 && a >= 1 && b >= 1 && a * b <= kMaxWavesPerBlock && c >= 0) {
       wx = a; wz = b; lw = c;
+      L.short_chunks_when_idle = false;
       if (n >= 4 && (v == 1 || v == 2 || v == 4) && d->nx % v == 0) vec = v;
       if (n >= 5) interleave = il ? 1 : 0;
     }
@@ -105,6 +108,11 @@ Layout make_layout(const stglbm_lattice_desc* d) {
     lw = (d->nz + wz * slots - 1) / (wz * slots);
   }
   L.lw = lw;
+  // Without statistics the z chunk only sets the block size; measured on
+  // MI355X, blocks streaming about 2 KB of each population row are fastest
+  // (one FP32 row of 512 cells, two FP16 rows).
+  const int row_bytes = d->nx * store_bytes(d->store);
+  L.lw_idle = row_bytes >= 2048 ? 1 : (2048 + row_bytes - 1) / row_bytes;
   L.slots = (d->nz + wz * lw - 1) / (wz * lw);
   L.zstep = interleave ? L.slots * wz : wz;
   L.nblocks = base * L.slots;
@@ -232,6 +240,15 @@ StepParams step_params(stglbm_t h) {
   p.vec = h->L.vec;
   p.nxt = h->L.nxt; p.wx = h->L.wx; p.wz = h->L.wz; p.nxg = h->L.nxg;
   p.slots = h->L.slots; p.lw = h->L.lw; p.zstep = h->L.zstep; p.nblocks = h->L.nblocks;
+  if (!h->sampling && h->L.short_chunks_when_idle) {
+    // The z chunk serves the statistics reduction (it sets the number of FP64
+    // slots).  Without statistics, short chunks stream fastest: the resident
+    // blocks then cover a narrow contiguous band of z slices.
+    p.lw = h->L.lw_idle;
+    p.slots = (d.nz + p.wz * p.lw - 1) / (p.wz * p.lw);
+    p.zstep = p.wz;
+    p.nblocks = h->L.nxg * d.ny * p.slots;
+  }
   p.remap = (p.nblocks % 8 == 0) ? 1 : 0;
   p.periodic_x = d.periodic_x;
   p.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
