@@ -18,6 +18,8 @@
 // FP32 cosine.  A block owns one row and 64 spanwise nodes; its 4 waves split
 // the modes, the row phasors and sigma^n are staged in LDS per chunk of modes,
 // and the waves' partial sums meet in LDS.
+#include <cstdlib>
+
 #include "stglbm_internal.h"
 
 namespace stglbm {
@@ -216,90 +218,111 @@ __global__ void inlet_zphase_kernel(SetupParams p) {
 
 // Inlet plane: v' = sqrt 6 sum_n sqrt(q^n) sigma^n cos(psi_n) (eq. aux_vec),
 // u' = a v' (eq. v_fluc), u_bc = (U + u') c_t / c_x (eqs. u_phys, u_transfer).
-// Block: 64 spanwise nodes of one row; wave w sums the modes n = w mod 8 with
-// four phasor loads in flight, then the 8 partial sums meet in LDS.
+// The phase splits into a row part (FP64 per row, mode and step, kept as the
+// FP32 phasor P = sqrt 6 sqrt(q) exp(i psi_row)) and the spanwise phasor
+// B = exp(i k d_z z) of the precomputed table, so cos(psi) = Re(P B) / |P|.
+// Block: kStgRows rows x 64 spanwise nodes; wave w sums the modes n = w mod 8
+// for all the block's rows, so each B loaded from the table serves kStgRows
+// rows; the 8 partial sums meet in LDS in a fixed order.  kStgRows is chosen
+// per plane so that the grid still has >= 2048 waves.
+template <int kStgRows>
 __global__ __launch_bounds__(64 * kStgWaves) void stg_plane_kernel(StgParams p) {
   const int lane = threadIdx.x;
   const int w = threadIdx.y;
   const int tid = w * 64 + lane;
-  const int j = blockIdx.y;
+  const int j0 = blockIdx.y * kStgRows;
   const int z = blockIdx.x * 64 + lane;
-  const bool active = z < p.nz;
-  const int zc = active ? z : p.nz - 1;
-  __shared__ float2 P[kStgChunk];
-  __shared__ float4 SG[kStgChunk];
-  __shared__ float red[3][kStgWaves][64];
-  const double yj = (j + 0.5) * p.c_x;
+  const int zc = z < p.nz ? z : p.nz - 1;
+  // modes staged per pass (LDS stays under 64 KiB per block)
+  constexpr int kChunk = kStgRows >= 4 ? kStgChunk / 2 : kStgChunk;
+  __shared__ float2 P[kStgRows][kChunk];
+  __shared__ float4 SG[kChunk];
+  __shared__ float red[kStgWaves][3 * kStgRows][64];
   const double sqrt6 = 2.449489742783178098;
-  const double* sq = p.sqrtq + (long long)j * p.n_modes;
-  float v0 = 0.f, v1 = 0.f, v2 = 0.f;
-  for (int base = 0; base < p.n_modes; base += kStgChunk) {
-    const int cnt = min(kStgChunk, p.n_modes - base);
-    for (int m = tid; m < cnt; m += 64 * kStgWaves) {
-      const double* md = p.modes + (long long)(base + m) * kModeFields;
-      // row part of the phase: k d_y y_j + phi + 2 pi d_x (x_in - U_b t) / L_e
-      const double psi = md[0] * md[2] * yj + md[7] + md[1] * p.tphase;
-      double s, c;
-      sincos(psi, &s, &c);
-      const double a = sqrt6 * sq[base + m];
-      P[m] = make_float2(static_cast<float>(a * c), static_cast<float>(a * s));
-      SG[m] = p.sig[base + m];
+  float v[kStgRows][3];
+#pragma unroll
+  for (int r = 0; r < kStgRows; ++r) v[r][0] = v[r][1] = v[r][2] = 0.f;
+  for (int base = 0; base < p.n_modes; base += kChunk) {
+    const int cnt = min(kChunk, p.n_modes - base);
+    for (int e = tid; e < kStgRows * cnt; e += 64 * kStgWaves) {
+      const int r = e / cnt, m = e - r * cnt;
+      const int j = j0 + r;
+      float2 ph = make_float2(0.f, 0.f);
+      if (j < p.ny) {
+        const double* md = p.modes + (long long)(base + m) * kModeFields;
+        // row part of the phase: k d_y y_j + phi + 2 pi d_x (x_in - U_b t) / L_e
+        const double psi = md[0] * md[2] * ((j + 0.5) * p.c_x) + md[7] + md[1] * p.tphase;
+        double sn, cs;
+        sincos(psi, &sn, &cs);
+        const double a = sqrt6 * p.sqrtq[(long long)j * p.n_modes + base + m];
+        ph = make_float2(static_cast<float>(a * cs), static_cast<float>(a * sn));
+      }
+      P[r][m] = ph;
     }
+    for (int m = tid; m < cnt; m += 64 * kStgWaves) SG[m] = p.sig[base + m];
     __syncthreads();
     const float2* bz = p.bz + (long long)base * p.nz + zc;
     const long long step = (long long)kStgWaves * p.nz;
     int m = w;
     for (; m + 3 * kStgWaves < cnt; m += 4 * kStgWaves) {
-      const float2 B0 = bz[(long long)m * p.nz];
-      const float2 B1 = bz[(long long)m * p.nz + step];
-      const float2 B2 = bz[(long long)m * p.nz + 2 * step];
-      const float2 B3 = bz[(long long)m * p.nz + 3 * step];
-      const float2 Bs[4] = {B0, B1, B2, B3};
+      const float2 Bs[4] = {bz[(long long)m * p.nz], bz[(long long)m * p.nz + step],
+                            bz[(long long)m * p.nz + 2 * step], bz[(long long)m * p.nz + 3 * step]};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const float2 Pm = P[m + u * kStgWaves];
         const float4 S = SG[m + u * kStgWaves];
-        const float c = Pm.x * Bs[u].x - Pm.y * Bs[u].y;   // scaled cos of the full phase
-        v0 += S.x * c;
-        v1 += S.y * c;
-        v2 += S.z * c;
+#pragma unroll
+        for (int r = 0; r < kStgRows; ++r) {
+          const float2 Pm = P[r][m + u * kStgWaves];
+          const float c = Pm.x * Bs[u].x - Pm.y * Bs[u].y;   // scaled cos of the full phase
+          v[r][0] += S.x * c;
+          v[r][1] += S.y * c;
+          v[r][2] += S.z * c;
+        }
       }
     }
     for (; m < cnt; m += kStgWaves) {
       const float2 B = bz[(long long)m * p.nz];
-      const float2 Pm = P[m];
       const float4 S = SG[m];
-      const float c = Pm.x * B.x - Pm.y * B.y;
-      v0 += S.x * c;
-      v1 += S.y * c;
-      v2 += S.z * c;
+#pragma unroll
+      for (int r = 0; r < kStgRows; ++r) {
+        const float2 Pm = P[r][m];
+        const float c = Pm.x * B.x - Pm.y * B.y;
+        v[r][0] += S.x * c;
+        v[r][1] += S.y * c;
+        v[r][2] += S.z * c;
+      }
     }
     __syncthreads();
   }
-  red[0][w][lane] = v0;
-  red[1][w][lane] = v1;
-  red[2][w][lane] = v2;
+#pragma unroll
+  for (int r = 0; r < kStgRows; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) red[w][3 * r + c][lane] = v[r][c];
   __syncthreads();
-  if (w == 0 && active) {
-    float v[3];
+  // one thread per (row, node) of the block: waves 0 .. kStgRows-1 take one row each
+  if (w < kStgRows) {
+    const int j = j0 + w;
+    if (j < p.ny && z < p.nz) {
+      float vs[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float acc = red[c][0][lane];
+      for (int c = 0; c < 3; ++c) {
+        float acc = red[0][3 * w + c][lane];
 #pragma unroll
-      for (int k = 1; k < kStgWaves; ++k) acc += red[c][k][lane];
-      v[c] = acc;
+        for (int k = 1; k < kStgWaves; ++k) acc += red[k][3 * w + c][lane];
+        vs[c] = acc;
+      }
+      const double* row = p.rows + (long long)j * kRowFields;
+      const double a11 = row[11], a21 = row[12], a22 = row[13], a31 = row[14], a32 = row[15], a33 = row[16];
+      const double u0 = row[0] + a11 * vs[0];
+      const double u1 = row[1] + a21 * vs[0] + a22 * vs[1];
+      const double u2 = row[2] + a31 * vs[0] + a32 * vs[1] + a33 * vs[2];
+      float* o = p.out + 3 * ((long long)j * p.nz + z);
+      const float ux = static_cast<float>(u0 * p.conv);
+      o[0] = ux;
+      o[1] = static_cast<float>(u1 * p.conv);
+      o[2] = static_cast<float>(u2 * p.conv);
+      if (!(fabsf(ux) < p.mach_limit)) atomicOr(p.flag, kFlagInletMach);
     }
-    const double* row = p.rows + (long long)j * kRowFields;
-    const double a11 = row[11], a21 = row[12], a22 = row[13], a31 = row[14], a32 = row[15], a33 = row[16];
-    const double u0 = row[0] + a11 * v[0];
-    const double u1 = row[1] + a21 * v[0] + a22 * v[1];
-    const double u2 = row[2] + a31 * v[0] + a32 * v[1] + a33 * v[2];
-    float* o = p.out + 3 * ((long long)j * p.nz + z);
-    const float ux = static_cast<float>(u0 * p.conv);
-    o[0] = ux;
-    o[1] = static_cast<float>(u1 * p.conv);
-    o[2] = static_cast<float>(u2 * p.conv);
-    if (!(fabsf(ux) < p.mach_limit)) atomicOr(p.flag, kFlagInletMach);
   }
 }
 
@@ -319,8 +342,19 @@ hipError_t launch_inlet_setup(const SetupParams& p, hipStream_t s) {
 
 hipError_t launch_stg(const StgParams& p, hipStream_t s) {
   const dim3 block(64, kStgWaves);
-  const dim3 grid((p.nz + 63) / 64, p.ny);
-  stg_plane_kernel<<<grid, block, 0, s>>>(p);
+  const long long zb = (p.nz + 63) / 64;
+  int rows = 4;
+  while (rows > 1 && zb * ((p.ny + rows - 1) / rows) * kStgWaves < 2048) rows /= 2;
+  if (const char* env = std::getenv("STGLBM_STG_ROWS")) {   // tuning override: 1, 2 or 4
+    const int r = std::atoi(env);
+    if (r == 1 || r == 2 || r == 4) rows = r;
+  }
+  const dim3 grid(static_cast<unsigned>(zb), static_cast<unsigned>((p.ny + rows - 1) / rows));
+  switch (rows) {
+    case 1: stg_plane_kernel<1><<<grid, block, 0, s>>>(p); break;
+    case 2: stg_plane_kernel<2><<<grid, block, 0, s>>>(p); break;
+    default: stg_plane_kernel<4><<<grid, block, 0, s>>>(p); break;
+  }
   return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@ constexpr int kRowFields = 18;      // U(3) k omega R(6) a(6) l_e
 constexpr int kModeFields = 8;      // k, d(3), sigma(3), phi
 constexpr int kScalars = 8;         // L_e k_min k_max alpha k_cut clamps U_b N
 constexpr int kMaxWavesPerBlock = 8; // step kernel: waves along x times waves along z
-constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel
+constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel (half for 4-row blocks)
 constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
 
 // Flag bits written by the kernels into the handle's status word.
