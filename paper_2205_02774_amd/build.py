@@ -17,6 +17,8 @@ FLAGS = [
     "-Wall",
 ]
 NOISE = "packed-fp32-ops"
+# roctx ranges around the host entry points (rocprofv3 --marker-trace)
+LINK = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def _run(cmd):
@@ -43,7 +45,7 @@ def build(verbose=False):
             if verbose and msgs.strip():
                 print(msgs, flush=True)
         tmp = LIB + ".tmp"
-        rc, msgs = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
+        rc, msgs = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, *LINK])
         if rc != 0:
             raise RuntimeError(f"link failed ({rc}):\n{msgs}")
     os.replace(tmp, LIB)

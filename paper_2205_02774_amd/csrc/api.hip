@@ -5,6 +5,8 @@
 // data for the test/ops helpers and report device flags.  Every step of the
 // method runs in the kernels of lattice_kernels.hip and inlet_kernels.hip.
 #include "stglbm.h"
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "stglbm_internal.h"
 
 #include <cmath>
@@ -24,6 +26,14 @@ constexpr uint32_t kCkptMagic = 0x5354474cu;   // "STGL"
 constexpr uint32_t kCkptVersion = 3;   // 2: store order [NZ][Q][NY][NX]; 3: velocity set and operator
 
 thread_local std::string g_lib_error;
+
+// roctx range over a host entry point (shown by rocprofv3 --marker-trace).
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePushA(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 struct Layout {
   uint64_t g[2] = {0, 0}, stats = 0, sponge = 0, flag = 0, ubc = 0, rans = 0, rows = 0, modes = 0,
@@ -366,6 +376,7 @@ int stglbm_init_lattice(const stglbm_lattice_desc* desc, void* d_workspace, uint
 }
 
 int stglbm_set_rans_inlet(stglbm_t h, const stglbm_rans_inlet* in) {
+  TraceRange trace("stglbm_set_rans_inlet");
   if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
   if (h->d.periodic_x) return fail(h, STGLBM_E_STATE, "periodic_x lattice has no inlet");
   if (!in || !in->y || !in->U3 || !in->k || !in->omega || !in->R6) return fail(h, STGLBM_E_INVAL, "null RANS input");
@@ -434,6 +445,7 @@ int stglbm_stg_generate(stglbm_t h, int64_t t_step, float* d_u_plane) {
 }
 
 int stglbm_step(stglbm_t h, int32_t n_steps) {
+  TraceRange trace("stglbm_step");
   if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
   if (n_steps < 0) return fail(h, STGLBM_E_INVAL, "n_steps < 0");
   if (!h->d.periodic_x && !h->inlet_ready) return fail(h, STGLBM_E_STATE, "set_rans_inlet must precede step");
@@ -521,6 +533,7 @@ int stglbm_stats_stop(stglbm_t h) {
 }
 
 int stglbm_get_stats(stglbm_t h, double* h_out, uint64_t n, int64_t* n_samples) {
+  TraceRange trace("stglbm_get_stats");
   if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
   const uint64_t bins = static_cast<uint64_t>(h->d.nx) * h->d.ny;
   if (!h_out || n != bins * 9) return fail(h, STGLBM_E_INVAL, "stats buffer must hold NX*NY*9 doubles");
@@ -674,6 +687,7 @@ int stglbm_checkpoint_size(stglbm_t h, uint64_t* bytes) {
 }
 
 int stglbm_checkpoint(stglbm_t h, void* h_buf, uint64_t n) {
+  TraceRange trace("stglbm_checkpoint");
   uint64_t need = 0;
   if (int rc = stglbm_checkpoint_size(h, &need)) return rc;
   if (!h_buf || n < need) return fail(h, STGLBM_E_INVAL, "checkpoint buffer too small");
@@ -694,6 +708,7 @@ int stglbm_checkpoint(stglbm_t h, void* h_buf, uint64_t n) {
 }
 
 int stglbm_restore(stglbm_t h, const void* h_buf, uint64_t n) {
+  TraceRange trace("stglbm_restore");
   if (!h || !h_buf) return fail(h, STGLBM_E_INVAL, "null argument");
   if (n < sizeof(CkptHeader)) return fail(h, STGLBM_E_INVAL, "checkpoint too short");
   CkptHeader hd;

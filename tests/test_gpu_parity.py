@@ -326,3 +326,21 @@ def test_error_paths():
                            n_modes=50, alpha=0.05, seed=0)
     assert e.value.code == abi.E_INVAL
     lat.close()
+
+
+def test_inlet_mach_guard_reported():
+    """An inlet plane with |u_x| >= 0.3 c_s (density_bc condition) is reported as STGLBM_E_UNSTABLE.
+
+    The condition is forced from the host: a lattice bulk velocity of 0.2 puts
+    the inlet centre-line velocity near 0.23, above 0.3 c_s = 0.173.
+    """
+    from paper_2205_02774_amd import abi
+    cfg = small_channel(24, 16, 8, n_modes=20, seed=4)
+    cfg["u_b_lb"] = 0.2
+    lat = _lat(cfg)
+    lat.step(1)
+    with pytest.raises(abi.StglbmError) as e:
+        lat.sync()
+    print(f"[gpu] inlet guard: {e.value}", flush=True)
+    assert e.value.code == abi.E_UNSTABLE and "inlet velocity" in str(e.value)
+    lat.close()
