@@ -39,8 +39,8 @@ struct Layout {
   uint64_t g[2] = {0, 0}, stats = 0, sponge = 0, flag = 0, ubc = 0, rans = 0, rows = 0, modes = 0,
            sqrtq = 0, bz = 0, sig = 0, scalars = 0, total = 0;
   int vec = 1, nxt = 0, wx = 1, wz = 1, nxg = 0, slots = 0, lw = 0, zstep = 1, nblocks = 0;
-  bool short_chunks_when_idle = true;   // steps without statistics: lw_idle z rows per block
-  int lw_idle = 1;
+  bool short_chunks_when_idle = true;   // steps without statistics: their own shape
+  int wx_idle = 1, nxg_idle = 1, lw_idle = 1;
 };
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -105,7 +105,19 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   if (set_size(d) != 19 || d->collision != 0) vec = 1;   // the variants are built for one cell per lane
   L.vec = vec;
   L.nxt = (d->nx + 64 * vec - 1) / (64 * vec);
-  if (wx == 0) wx = L.nxt < 8 ? L.nxt : 8;
+  const int wx_row = L.nxt < 8 ? L.nxt : 8;   // whole rows of up to 8 tiles
+  L.wx_idle = wx == 0 ? wx_row : wx;
+  if (wx == 0) {
+    // Steps that sample statistics: for FP32, half rows with two z waves per
+    // block halve the FP64 slots at the same block count (measured 0.535 ->
+    // 0.528 ms on 512x128x256); 16-bit stores keep whole rows (0.309 vs 0.322 ms).
+    if (d->store == STGLBM_F32 && wx_row >= 2) {
+      wx = wx_row / 2;
+      wz = 2;
+    } else {
+      wx = wx_row;
+    }
+  }
   L.wx = wx;
   L.wz = wz;
   L.nxg = (L.nxt + wx - 1) / wx;
@@ -123,6 +135,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   // (one FP32 row of 512 cells, two FP16 rows).
   const int row_bytes = d->nx * store_bytes(d->store);
   L.lw_idle = row_bytes >= 2048 ? 1 : (2048 + row_bytes - 1) / row_bytes;
+  L.nxg_idle = (L.nxt + L.wx_idle - 1) / L.wx_idle;
   L.slots = (d->nz + wz * lw - 1) / (wz * lw);
   L.zstep = interleave ? L.slots * wz : wz;
   L.nblocks = base * L.slots;
@@ -251,13 +264,17 @@ StepParams step_params(stglbm_t h) {
   p.nxt = h->L.nxt; p.wx = h->L.wx; p.wz = h->L.wz; p.nxg = h->L.nxg;
   p.slots = h->L.slots; p.lw = h->L.lw; p.zstep = h->L.zstep; p.nblocks = h->L.nblocks;
   if (!h->sampling && h->L.short_chunks_when_idle) {
-    // The z chunk serves the statistics reduction (it sets the number of FP64
-    // slots).  Without statistics, short chunks stream fastest: the resident
-    // blocks then cover a narrow contiguous band of z slices.
+    // The block shape and z chunk serve the statistics reduction (they set the
+    // number of FP64 slots).  Without statistics, whole-row blocks with short
+    // chunks stream fastest: the resident blocks then cover a narrow
+    // contiguous band of z slices.
+    p.wx = h->L.wx_idle;
+    p.wz = 1;
+    p.nxg = h->L.nxg_idle;
     p.lw = h->L.lw_idle;
-    p.slots = (d.nz + p.wz * p.lw - 1) / (p.wz * p.lw);
-    p.zstep = p.wz;
-    p.nblocks = h->L.nxg * d.ny * p.slots;
+    p.slots = (d.nz + p.lw - 1) / p.lw;
+    p.zstep = 1;
+    p.nblocks = p.nxg * d.ny * p.slots;
   }
   p.remap = (p.nblocks % 8 == 0) ? 1 : 0;
   p.periodic_x = d.periodic_x;
