@@ -264,11 +264,13 @@ __global__ __launch_bounds__(64 * kStgWaves) void stg_plane_kernel(StgParams p) 
     const float2* bz = p.bz + (long long)base * p.nz + zc;
     const long long step = (long long)kStgWaves * p.nz;
     int m = w;
-    for (; m + 3 * kStgWaves < cnt; m += 4 * kStgWaves) {
-      const float2 Bs[4] = {bz[(long long)m * p.nz], bz[(long long)m * p.nz + step],
-                            bz[(long long)m * p.nz + 2 * step], bz[(long long)m * p.nz + 3 * step]};
+    constexpr int kInFlight = 8;   // phasor loads in flight per wave
+    for (; m + (kInFlight - 1) * kStgWaves < cnt; m += kInFlight * kStgWaves) {
+      float2 Bs[kInFlight];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kInFlight; ++u) Bs[u] = bz[(long long)m * p.nz + u * step];
+#pragma unroll
+      for (int u = 0; u < kInFlight; ++u) {
         const float4 S = SG[m + u * kStgWaves];
 #pragma unroll
         for (int r = 0; r < kStgRows; ++r) {
