@@ -17,6 +17,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import subprocess
 import sys
 import time
@@ -35,11 +36,25 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+_CODE_TOKENS = re.compile(r'"(?:\\.|[^"\\])*"|//[^\n]*|/\*.*?\*/', re.S)
+
+
+def code_text(source):
+    """C++ source without its comments, white space collapsed (string literals kept)."""
+    text = _CODE_TOKENS.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", source)
+    return " ".join(text.split())
+
+
 def kernel_hash():
-    """Hash of the sources of the stream-collide kernel (its header and the unit that instantiates it)."""
+    """Hash of the code of the stream-collide kernel (its header and the unit that instantiates it).
+
+    Comments are dropped and white space collapsed first, so that a change of
+    wording alone keeps the counter record of an unchanged kernel valid.
+    """
     h = hashlib.sha256()
     for path in KERNEL_SRCS:
-        h.update(open(path, "rb").read())
+        h.update(code_text(open(path).read()).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 

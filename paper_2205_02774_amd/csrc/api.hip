@@ -50,7 +50,7 @@ int store_bytes(int store) { return store == STGLBM_F32 ? 4 : 2; }
 // Populations of the descriptor's velocity set (0 selects D3Q19).
 int set_size(const stglbm_lattice_desc* d) { return d->velocity_set == 0 ? 19 : d->velocity_set; }
 
-// The step kernel addresses one z slice of the store ([19][NY][NX] values)
+// The step kernel addresses one z slice of the store ([Q][NY][NX] values)
 // through a raw buffer resource of at most 4 GiB - 1.
 bool slice_fits(const stglbm_lattice_desc* d) {
   return static_cast<uint64_t>(set_size(d)) * d->nx * d->ny * store_bytes(d->store) <= 0xffffffffull;

@@ -264,7 +264,7 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
   const int xt = xg * p.wx + wxi;
   const bool wave_live = xt < p.nxt;        // waves past the last x tile only join the reduction
   const int nx = p.nx, ny = p.ny, nz = p.nz;
-  // The store is [NZ][19][NY][NX]: one z slice holds all 19 populations.  A
+  // The store is [NZ][Q][NY][NX]: one z slice holds all Q populations.  A
   // raw buffer resource spans one slice (under 4 GiB); the scalar offset is
   // population * NY NX + row start, the per-lane offset is x.
   const unsigned pop_bytes = static_cast<unsigned>(p.plane2d) * SB;

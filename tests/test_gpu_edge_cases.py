@@ -1,0 +1,84 @@
+"""Degenerate sizes against the oracle: the smallest legal lattices, a single
+spanwise slice (z - 1 = z = z + 1), and zero steps."""
+
+import numpy as np
+import pytest
+
+from oracle import OracleChannel
+from workloads.configs import small_channel
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return np.abs(a - b) / np.abs(b)
+
+
+@pytest.mark.parametrize("shape", [(2, 2, 1), (3, 2, 1), (5, 3, 1), (2, 2, 3)])
+def test_smallest_periodic_lattices(shape):
+    from paper_2205_02774_amd import Lattice
+    from oracle.lattice import W
+    nx, ny, nz = shape
+    nu, cs, force = 2e-2, 0.1, (1e-5, 0.0, 0.0)
+    print(f"[gpu] edge periodic {shape}", flush=True)
+    lat = Lattice(nx, ny, nz, device="cuda:0", periodic_x=True, nu_lb=nu, cs_smag=cs, force=force)
+    ora = OracleChannel(nx, ny, nz, nu_lb=nu, cs_smag=cs, force=force, periodic_x=True)
+    rng = np.random.default_rng(1)
+    lat.set_f(W[:, None, None, None] * (1.0 + 1e-2 * rng.uniform(-1, 1, (19, nz, ny, nx))))
+    ora.set_f(lat.get_f())
+    lat.stats_reset()
+    ora.stats_reset()
+    lat.step(50)
+    ora.step(50)
+    rel = _rel(lat.get_f(), ora.f)
+    st, n = lat.get_stats()
+    print(f"[gpu] edge periodic {shape}: max rel err f {rel.max():.3e}", flush=True)
+    assert rel.max() < 1e-6 and n == 50
+    np.testing.assert_allclose(st, ora.stats, rtol=0, atol=1e-6 * np.abs(ora.stats).max() + 1e-12)
+    lat.close()
+
+
+@pytest.mark.parametrize("shape", [(2, 4, 1), (3, 6, 2), (65, 4, 1)])
+def test_smallest_inlet_outlet_channels(shape):
+    """Inlet and outlet planes adjacent (NX = 2) or one cell apart, single spanwise slice.
+
+    Channels this small are far from resolved: the inlet drives the populations
+    far from equilibrium (|f - w| up to 3 w, some f below zero), and FP32
+    rounding grows by about 1e-7 per step, so a free run drifts past 1e-6 within
+    ten steps however exact the kernel is.  The map itself is checked instead:
+    both sides step in lockstep and the oracle restarts from the GPU state
+    before every step, so each comparison holds one step of rounding.  The
+    scale of population i is max(|f_i|, w_i): the store holds f - w and the
+    arithmetic works on terms of size w_i, so f_i near zero has no smaller floor.
+    """
+    from paper_2205_02774_amd import channel_from_config
+    from oracle.lattice import W
+    nx, ny, nz = shape
+    cfg = small_channel(nx, ny, nz, n_modes=5, seed=9)
+    cfg["sponge_cells"] = min(cfg["sponge_cells"], nx - 2)   # the sponge must end before the inlet
+    print(f"[gpu] edge channel {cfg['name']}", flush=True)
+    lat = channel_from_config(cfg, device="cuda:0")
+    ora = OracleChannel.from_config(cfg)
+    scale_w = W[:, None, None, None]
+    worst = 0.0
+    for _ in range(30):
+        lat.step(1)
+        ora.step(1)
+        f = lat.get_f()
+        worst = max(worst, float((np.abs(f - ora.f) / np.maximum(np.abs(ora.f), scale_w)).max()))
+        ora.set_f(f)
+    print(f"[gpu] edge channel {cfg['name']}: max one-step rel err f {worst:.3e}", flush=True)
+    assert worst < 1e-6
+    assert ora.t == 30
+    lat.close()
+
+
+def test_zero_steps_is_a_no_op():
+    from paper_2205_02774_amd import channel_from_config
+    cfg = small_channel(16, 8, 4, n_modes=5, seed=2)
+    lat = channel_from_config(cfg, device="cuda:0")
+    lat.step(3)
+    f0 = lat.get_f()
+    lat.step(0)
+    np.testing.assert_array_equal(lat.get_f(), f0)
+    lat.close()
