@@ -144,15 +144,19 @@ int stglbm_set_rans_inlet(stglbm_t h, const stglbm_rans_inlet* in);
 /* Inlet velocity plane at step index t_step (the state being produced),
  * eqs. aux_vec, psu, v_fluc, u_phys, u_transfer, in lattice units.
  * Writes [NY][NZ][3] FP32 to d_u_plane (device) if non-null, else to the
- * handle's own inlet buffer.  Asynchronous on the stream. */
+ * handle's own inlet buffer (the planes stglbm_step made ahead are then
+ * made again when needed).  Asynchronous on the stream.  The inlet guard
+ * |u_x| < 0.3 c_s is applied by stglbm_step, to the planes it uses. */
 int stglbm_stg_generate(stglbm_t h, int64_t t_step, float* d_u_plane);
 
 /* Advance n_steps time steps (Algorithm 1, steps 5-12): for each step the STG
- * plane at t+1, then one fused pass: pull streaming with bounce-back walls and
- * spanwise wrap, regularized inlet rebuild (eqs. f_i .. bc_eq), regularized
- * pressure outlet, moments, Smagorinsky tau_eff (eqs. strain, tau_eff), the
- * sponge (eq. sponge_visco), regularized BGK collision with Guo force, and,
- * while sampling, FP64 statistics.  Asynchronous on the stream. */
+ * plane at t+1 (one launch makes the planes of 8 consecutive steps, kept until
+ * used, also by later calls), then one fused pass: pull streaming with
+ * bounce-back walls and spanwise wrap, regularized inlet rebuild (eqs. f_i ..
+ * bc_eq) behind the guard |u_x| < 0.3 c_s, regularized pressure outlet,
+ * moments, Smagorinsky tau_eff (eqs. strain, tau_eff), the sponge (eq.
+ * sponge_visco), regularized BGK collision with Guo force, and, while
+ * sampling, FP64 statistics.  Asynchronous on the stream. */
 int stglbm_step(stglbm_t h, int32_t n_steps);
 
 /* Zero the statistics and start sampling every subsequent step. */
@@ -228,8 +232,9 @@ int stglbm_checkpoint(stglbm_t h, void* h_buf, uint64_t n);
 int stglbm_restore(stglbm_t h, const void* h_buf, uint64_t n);
 
 /* Timing of the fused step kernel and the STG kernel with HIP events on the
- * handle's stream while enabled.  out[4] = {step-kernel ms total, launches,
- * STG-kernel ms total, launches}; reading synchronizes and clears. */
+ * handle's stream while enabled.  out[5] = {step-kernel ms total, launches,
+ * STG-kernel ms total, inlet planes generated, STG launches}; reading
+ * synchronizes and clears.  n >= 5. */
 int stglbm_profile(stglbm_t h, int32_t enable);
 int stglbm_profile_read(stglbm_t h, double* out, uint64_t n);
 

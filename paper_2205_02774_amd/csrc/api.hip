@@ -152,7 +152,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   L.sponge = take(static_cast<uint64_t>(d->nx) * sizeof(float));
   L.flag = take(2 * sizeof(int));
   if (!d->periodic_x) {
-    L.ubc = take(static_cast<uint64_t>(d->ny) * d->nz * 3 * sizeof(float));
+    L.ubc = take(static_cast<uint64_t>(kStgBatch) * d->ny * d->nz * 3 * sizeof(float));
     L.rans = take(static_cast<uint64_t>(d->max_rans) * 12 * sizeof(double));
     L.rows = take(static_cast<uint64_t>(d->ny) * kRowFields * sizeof(double));
     L.modes = take(static_cast<uint64_t>(d->max_modes) * kModeFields * sizeof(double));
@@ -206,13 +206,18 @@ struct stglbm_ctx {
   int probe_xyz[kMaxProbes][3] = {};
   float* probe_out = nullptr;
   int64_t probe_capacity = 0, probe_rows = 0;
-  size_t n_step = 0, n_stg = 0;
+  size_t n_step = 0, n_stg = 0, n_planes = 0;
+  // Inlet planes of the steps ring_t0 .. ring_t0 + ring_n - 1, made by one STG
+  // launch ahead of use (ring_n = 0: none valid).
+  int64_t ring_t0 = 0;
+  int ring_n = 0;
 
   template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
   void* gbuf(int k) { return ws + L.g[k]; }
   uint64_t cells() const { return static_cast<uint64_t>(d.nx) * d.ny * d.nz; }
   int q() const { return set_size(&d); }
   uint64_t gbytes() const { return static_cast<uint64_t>(q()) * cells() * store_bytes(d.store); }
+  uint64_t plane_floats() const { return static_cast<uint64_t>(d.ny) * d.nz * 3; }
 };
 
 namespace {
@@ -289,28 +294,31 @@ StepParams step_params(stglbm_t h) {
   p.fz = static_cast<float>(d.force[2]);
   p.rho_out_m1 = static_cast<float>(d.rho_out - 1.0);
   p.inv_rho_out = static_cast<float>(1.0 / d.rho_out);
+  p.mach_limit = static_cast<float>(0.3 / std::sqrt(3.0));
   p.sponge = h->at<float>(h->L.sponge);
-  p.ubc = d.periodic_x ? nullptr : h->at<float>(h->L.ubc);
+  p.ubc = nullptr;   // set per step from the plane ring
   p.stats = h->at<double>(h->L.stats);
   p.flag = h->at<int>(h->L.flag);
   return p;
 }
 
-int launch_plane(stglbm_t h, int64_t t_step, float* out) {
+// STG planes of the n consecutive steps t_first .. t_first + n - 1, written
+// one after the other to out (n <= kStgBatch), in one launch.
+int launch_planes(stglbm_t h, int64_t t_first, int n, float* out) {
   StgParams s{};
   s.modes = h->at<double>(h->L.modes);
   s.sqrtq = h->at<double>(h->L.sqrtq);
   s.bz = h->at<float2>(h->L.bz);
   s.sig = h->at<float4>(h->L.sig);
   s.rows = h->at<double>(h->L.rows);
-  s.out = out ? out : h->at<float>(h->L.ubc);
-  s.flag = h->at<int>(h->L.flag);
+  s.out = out;
   s.ny = h->d.ny; s.nz = h->d.nz; s.n_modes = h->n_modes;
+  s.n_planes = n;
   s.c_x = h->c_x;
   s.conv = h->c_t / h->c_x;
   const double kTwoPi = 6.283185307179586476925;
-  s.tphase = kTwoPi * (0.0 - h->U_b * (static_cast<double>(t_step) * h->c_t)) / h->L_e;
-  s.mach_limit = static_cast<float>(0.3 / std::sqrt(3.0));
+  for (int b = 0; b < n; ++b)
+    s.tphase[b] = kTwoPi * (0.0 - h->U_b * (static_cast<double>(t_first + b) * h->c_t)) / h->L_e;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->prof) {
     e0 = pooled_event(h->ev_stg, 2 * h->n_stg);
@@ -321,7 +329,21 @@ int launch_plane(stglbm_t h, int64_t t_step, float* out) {
   if (h->prof && e0 && e1) {
     HIP_CHECK(h, hipEventRecord(e1, h->stream), "hipEventRecord");
     ++h->n_stg;
+    h->n_planes += static_cast<size_t>(n);
   }
+  return STGLBM_OK;
+}
+
+// Inlet plane of step t (device pointer into the ring), generating the next
+// kStgBatch planes first if t is not held.
+int ring_plane(stglbm_t h, int64_t t, const float** plane) {
+  if (h->ring_n == 0 || t < h->ring_t0 || t >= h->ring_t0 + h->ring_n) {
+    h->ring_n = 0;
+    if (int rc = launch_planes(h, t, kStgBatch, h->at<float>(h->L.ubc))) return rc;
+    h->ring_t0 = t;
+    h->ring_n = kStgBatch;
+  }
+  *plane = h->at<float>(h->L.ubc) + static_cast<uint64_t>(t - h->ring_t0) * h->plane_floats();
   return STGLBM_OK;
 }
 
@@ -452,13 +474,15 @@ int stglbm_set_rans_inlet(stglbm_t h, const stglbm_rans_inlet* in) {
   hs = fnv1a(hs, &in->n_modes, sizeof(in->n_modes));
   h->inlet_hash = hs;
   h->inlet_ready = true;
+  h->ring_n = 0;
   return rc;
 }
 
 int stglbm_stg_generate(stglbm_t h, int64_t t_step, float* d_u_plane) {
   if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
   if (h->d.periodic_x || !h->inlet_ready) return fail(h, STGLBM_E_STATE, "no inlet installed");
-  return launch_plane(h, t_step, d_u_plane);
+  if (!d_u_plane) h->ring_n = 0;   // the plane goes to the front of the ring
+  return launch_planes(h, t_step, 1, d_u_plane ? d_u_plane : h->at<float>(h->L.ubc));
 }
 
 int stglbm_step(stglbm_t h, int32_t n_steps) {
@@ -467,11 +491,10 @@ int stglbm_step(stglbm_t h, int32_t n_steps) {
   if (n_steps < 0) return fail(h, STGLBM_E_INVAL, "n_steps < 0");
   if (!h->d.periodic_x && !h->inlet_ready) return fail(h, STGLBM_E_STATE, "set_rans_inlet must precede step");
   for (int32_t s = 0; s < n_steps; ++s) {
-    if (!h->d.periodic_x) {
-      const int rc = launch_plane(h, h->t + 1, nullptr);
-      if (rc) return rc;
-    }
     StepParams p = step_params(h);
+    if (!h->d.periodic_x) {
+      if (int rc = ring_plane(h, h->t + 1, &p.ubc)) return rc;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->prof) {
       e0 = pooled_event(h->ev_step, 2 * h->n_step);
@@ -689,6 +712,7 @@ int stglbm_set_stream(stglbm_t h, void* hip_stream) {
   if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
   HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   h->stream = static_cast<hipStream_t>(hip_stream);
+  h->ring_n = 0;   // planes made on the old stream are not ordered before work on the new one
   return STGLBM_OK;
 }
 
@@ -747,6 +771,7 @@ int stglbm_restore(stglbm_t h, const void* h_buf, uint64_t n) {
   HIP_CHECK(h, launch_fill_zero(h->at<char>(h->L.flag), kAlign, h->stream), "flag reset");
   HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   h->t = hd.t;
+  h->ring_n = 0;
   h->n_samples = hd.n_samples;
   h->sampling = hd.sampling != 0;
   return STGLBM_OK;
@@ -759,7 +784,7 @@ int stglbm_profile(stglbm_t h, int32_t enable) {
 }
 
 int stglbm_profile_read(stglbm_t h, double* out, uint64_t n) {
-  if (!h || !out || n < 4) return fail(h, STGLBM_E_INVAL, "profile buffer must hold 4 doubles");
+  if (!h || !out || n < 5) return fail(h, STGLBM_E_INVAL, "profile buffer must hold 5 doubles");
   HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   double ms_step = 0.0, ms_stg = 0.0;
   for (size_t i = 0; i < h->n_step; ++i) {
@@ -773,8 +798,8 @@ int stglbm_profile_read(stglbm_t h, double* out, uint64_t n) {
     ms_stg += ms;
   }
   out[0] = ms_step; out[1] = static_cast<double>(h->n_step);
-  out[2] = ms_stg; out[3] = static_cast<double>(h->n_stg);
-  h->n_step = h->n_stg = 0;
+  out[2] = ms_stg; out[3] = static_cast<double>(h->n_planes); out[4] = static_cast<double>(h->n_stg);
+  h->n_step = h->n_stg = h->n_planes = 0;
   return STGLBM_OK;
 }
 

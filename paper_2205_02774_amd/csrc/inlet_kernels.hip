@@ -221,10 +221,12 @@ __global__ void inlet_zphase_kernel(SetupParams p) {
 // The phase splits into a row part (FP64 per row, mode and step, kept as the
 // FP32 phasor P = sqrt 6 sqrt(q) exp(i psi_row)) and the spanwise phasor
 // B = exp(i k d_z z) of the precomputed table, so cos(psi) = Re(P B) / |P|.
-// Block: kStgRows rows x 64 spanwise nodes; wave w sums the modes n = w mod 8
-// for all the block's rows, so each B loaded from the table serves kStgRows
-// rows; the 8 partial sums meet in LDS in a fixed order.  kStgRows is chosen
-// per plane so that the grid still has >= 2048 waves.
+// Block: kStgRows rows x 64 spanwise nodes of one plane; wave w sums the
+// modes n = w mod 8 for all the block's rows, so each B loaded from the table
+// serves kStgRows rows; the 8 partial sums meet in LDS in a fixed order.  One
+// launch writes n_planes consecutive steps (grid z); kStgRows is chosen so
+// that the grid still has >= 2048 waves.  The inlet guard |u_x| < 0.3 c_s is
+// applied where a plane is used, by the step kernel.
 template <int kStgRows>
 __global__ __launch_bounds__(64 * kStgWaves) void stg_plane_kernel(StgParams p) {
   const int lane = threadIdx.x;
@@ -232,6 +234,7 @@ __global__ __launch_bounds__(64 * kStgWaves) void stg_plane_kernel(StgParams p) 
   const int tid = w * 64 + lane;
   const int j0 = blockIdx.y * kStgRows;
   const int z = blockIdx.x * 64 + lane;
+  const double tphase = p.tphase[blockIdx.z];
   const int zc = z < p.nz ? z : p.nz - 1;
   // modes staged per pass (LDS stays under 64 KiB per block)
   constexpr int kChunk = kStgRows >= 4 ? kStgChunk / 2 : kStgChunk;
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(64 * kStgWaves) void stg_plane_kernel(StgParams p) 
       if (j < p.ny) {
         const double* md = p.modes + (long long)(base + m) * kModeFields;
         // row part of the phase: k d_y y_j + phi + 2 pi d_x (x_in - U_b t) / L_e
-        const double psi = md[0] * md[2] * ((j + 0.5) * p.c_x) + md[7] + md[1] * p.tphase;
+        const double psi = md[0] * md[2] * ((j + 0.5) * p.c_x) + md[7] + md[1] * tphase;
         double sn, cs;
         sincos(psi, &sn, &cs);
         const double a = sqrt6 * p.sqrtq[(long long)j * p.n_modes + base + m];
@@ -318,12 +321,10 @@ __global__ __launch_bounds__(64 * kStgWaves) void stg_plane_kernel(StgParams p) 
       const double u0 = row[0] + a11 * vs[0];
       const double u1 = row[1] + a21 * vs[0] + a22 * vs[1];
       const double u2 = row[2] + a31 * vs[0] + a32 * vs[1] + a33 * vs[2];
-      float* o = p.out + 3 * ((long long)j * p.nz + z);
-      const float ux = static_cast<float>(u0 * p.conv);
-      o[0] = ux;
+      float* o = p.out + 3 * ((long long)blockIdx.z * p.ny * p.nz + (long long)j * p.nz + z);
+      o[0] = static_cast<float>(u0 * p.conv);
       o[1] = static_cast<float>(u1 * p.conv);
       o[2] = static_cast<float>(u2 * p.conv);
-      if (!(fabsf(ux) < p.mach_limit)) atomicOr(p.flag, kFlagInletMach);
     }
   }
 }
@@ -345,13 +346,15 @@ hipError_t launch_inlet_setup(const SetupParams& p, hipStream_t s) {
 hipError_t launch_stg(const StgParams& p, hipStream_t s) {
   const dim3 block(64, kStgWaves);
   const long long zb = (p.nz + 63) / 64;
+  if (p.n_planes < 1 || p.n_planes > kStgBatch) return hipErrorInvalidValue;
   int rows = 4;
-  while (rows > 1 && zb * ((p.ny + rows - 1) / rows) * kStgWaves < 2048) rows /= 2;
+  while (rows > 1 && zb * ((p.ny + rows - 1) / rows) * p.n_planes * kStgWaves < 2048) rows /= 2;
   if (const char* env = std::getenv("STGLBM_STG_ROWS")) {   // tuning override: 1, 2 or 4
     const int r = std::atoi(env);
     if (r == 1 || r == 2 || r == 4) rows = r;
   }
-  const dim3 grid(static_cast<unsigned>(zb), static_cast<unsigned>((p.ny + rows - 1) / rows));
+  const dim3 grid(static_cast<unsigned>(zb), static_cast<unsigned>((p.ny + rows - 1) / rows),
+                  static_cast<unsigned>(p.n_planes));
   switch (rows) {
     case 1: stg_plane_kernel<1><<<grid, block, 0, s>>>(p); break;
     case 2: stg_plane_kernel<2><<<grid, block, 0, s>>>(p); break;

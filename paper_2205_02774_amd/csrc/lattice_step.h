@@ -306,6 +306,7 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
 #pragma unroll
     for (int k = 0; k < V; ++k) acc[q][k] = 0.0f;
   int bad = 0;
+  int bad_inlet = 0;
 
   // The block's waves take wz consecutive z rows and march lw times by zstep:
   // zstep = slots * wz interleaves the blocks of one (x group, y) over z, so
@@ -386,6 +387,7 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
       ubx = u[0];
       uby = u[1];
       ubz = u[2];
+      bad_inlet |= !(__builtin_fabsf(ubx) < p.mach_limit);   // density_bc needs |u_x| well below c_s
     }
 
     unsigned out[QN][NW];
@@ -574,6 +576,9 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
   // one flag write per wave
   if (__any(bad && active && wave_live)) {
     if (lane == 0) atomicOr(p.flag, kFlagDensity);
+  }
+  if (__any(bad_inlet)) {
+    if (lane == 0) atomicOr(p.flag, kFlagInletMach);
   }
 
   if (STATS) {

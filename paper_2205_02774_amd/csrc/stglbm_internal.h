@@ -12,6 +12,7 @@ constexpr int kScalars = 8;         // L_e k_min k_max alpha k_cut clamps U_b N
 constexpr int kMaxWavesPerBlock = 8; // step kernel: waves along x times waves along z
 constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel (half for 4-row blocks)
 constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
+constexpr int kStgBatch = 8;        // inlet planes generated per STG launch during stepping
 
 // Flag bits written by the kernels into the handle's status word.
 constexpr int kFlagDensity = 1;     // |rho - 1| >= 0.5 or NaN in the step kernel
@@ -42,8 +43,9 @@ struct StepParams {
   float fx, fy, fz;         // Guo acceleration
   float rho_out_m1;         // rho_out - 1
   float inv_rho_out;        // 1/rho_out
+  float mach_limit;         // inlet guard: |u_bc,x| < 0.3 c_s
   const float* sponge;      // [NX] viscosity multipliers (all 1 if no sponge)
-  const float* ubc;         // [NY][NZ][3] inlet velocity (lattice units)
+  const float* ubc;         // [NY][NZ][3] inlet velocity of this step (lattice units)
   double* stats;            // [slots][9][NY][NX] FP64 sums
   int* flag;
 };
@@ -66,13 +68,12 @@ struct StgParams {
   const float2* bz;         // [N][NZ] spanwise phasors exp(i k d_z z)
   const float4* sig;        // [N] sigma^n in FP32 (x, y, z, 0)
   const double* rows;       // [NY][18]
-  float* out;               // [NY][NZ][3]
-  int* flag;
+  float* out;               // n_planes planes [NY][NZ][3], one after the other
   int ny, nz, n_modes;
+  int n_planes;             // 1 .. kStgBatch consecutive steps
   double c_x;               // lattice spacing (m)
   double conv;              // c_t / c_x
-  double tphase;            // 2 pi (x_in - U_b t) / L_e for this step
-  float mach_limit;         // 0.3 c_s
+  double tphase[kStgBatch]; // 2 pi (x_in - U_b t) / L_e for the step of each plane
 };
 
 // One-off inlet precompute.

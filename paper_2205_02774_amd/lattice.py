@@ -242,10 +242,11 @@ class Lattice:
         self._chk(self.lib.stglbm_profile(self.handle, 1 if enable else 0))
 
     def profile_read(self):
-        """{'step_ms', 'step_launches', 'stg_ms', 'stg_launches'} since the last read."""
-        out = np.zeros(4)
-        self._chk(self.lib.stglbm_profile_read(self.handle, _dptr(out), 4))
-        return {"step_ms": out[0], "step_launches": int(out[1]), "stg_ms": out[2], "stg_launches": int(out[3])}
+        """{'step_ms', 'step_launches', 'stg_ms', 'stg_planes', 'stg_launches'} since the last read."""
+        out = np.zeros(5)
+        self._chk(self.lib.stglbm_profile_read(self.handle, _dptr(out), 5))
+        return {"step_ms": out[0], "step_launches": int(out[1]), "stg_ms": out[2], "stg_planes": int(out[3]),
+                "stg_launches": int(out[4])}
 
 
 def channel_from_config(cfg, *, store=None, device="cuda", stream=None, periodic_x=False, max_modes=None,
