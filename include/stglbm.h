@@ -218,7 +218,8 @@ int stglbm_get_sqrtq(stglbm_t h, double* h_out, uint64_t n);
 /* Completed steps. */
 int stglbm_get_step(stglbm_t h, int64_t* t);
 
-/* Switch the handle to another caller-owned stream. */
+/* Switch the handle to another caller-owned stream (waits for the old one
+ * first). */
 int stglbm_set_stream(stglbm_t h, void* hip_stream);
 
 /* Wait for the stream and report a device-side instability. */

@@ -236,11 +236,12 @@ __device__ __forceinline__ unsigned from_next_lane(unsigned v) {
 
 // Mapping: lane l of the wave at x tile t owns the V consecutive cells
 // x0 = (64 t + l) V .. x0 + V - 1 of one (y, z) row, so each population load
-// and store of a lane is one V-element vector (8 bytes by default) and a
-// wave's access is one contiguous 64 V-element segment.  Pull streaming
-// shifts by one cell along x: the element that crosses a lane boundary comes
-// from the neighbouring lane by a DPP shift, and only the first and last
-// lanes of a wave load it from memory.
+// and store of a lane is one V-element vector and a wave's access is one
+// contiguous 64 V-element segment.  With V = 1 (the default) a lane loads the
+// source cell x - c_x itself.  With V > 1, pull streaming shifts by one cell
+// along x: the element that crosses a lane boundary comes from the
+// neighbouring lane by a DPP shift, and only the first and last lanes of a
+// wave load it from memory.
 template <class Codec, int QN, bool REG, int V, bool STATS, bool FORCE>
 __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams p) {
   using S = typename Codec::storage;
