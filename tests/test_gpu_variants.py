@@ -88,3 +88,32 @@ def test_poiseuille_closed_form(q, operator, tau):
     # rounds every full population (1 - 1/tau) g + g_eq/tau each step, and those errors
     # are not confined to the hydrodynamic moments, so its fixed point sits further out.
     assert err < (5e-5 if operator == "bgk" else 1e-5)
+
+
+@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("store,unit", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
+def test_half_store_variant_channel(q, store, unit):
+    """D3Q15/D3Q27 with FP16/BF16 deviation stores against the FP64 oracle.
+
+    The bound is the one derived for the D3Q19 half stores: every step rounds
+    each stored g_i to nearest (relative half-ulp `unit`), moving f_i by at
+    most unit |g_i| / f_i, and K independent roundings stay within
+    4 sqrt(K) unit max_t max_i |g_i / f_i|.
+    """
+    from paper_2205_02774_amd import channel_from_config
+    cfg = small_channel(40, 12, 8, n_modes=20, seed=2)
+    print(f"[gpu] variant D3Q{q} {store}: channel {cfg['name']}", flush=True)
+    lat = channel_from_config(cfg, device="cuda:0", store=store, velocity_set=q)
+    ora = OracleChannel.from_config(cfg, velocity_set=q)
+    W = OL.velocity_set(q).W[:, None, None, None]
+    K = 20
+    ratio = 0.0
+    for _ in range(K):
+        ora.step(1)
+        ratio = max(ratio, float(np.max(np.abs(ora.f - W) / ora.f)))
+    lat.step(K)
+    rel = _rel(lat.get_f(), ora.f)
+    bound = 4.0 * np.sqrt(K) * unit * ratio
+    print(f"[gpu] D3Q{q} {store}: max rel err after {K} steps {rel.max():.3e}, bound {bound:.3e}", flush=True)
+    assert rel.max() < bound
+    lat.close()
