@@ -311,7 +311,7 @@ def main():
     ap.add_argument("--precision-steps", type=int, default=0,
                     help="if > 0: sampled steps of the FP16/BF16-vs-FP32 profile comparison (after 20k warm-up)")
     ap.add_argument("--cpu-nz", type=int, default=32)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=12)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported (the x-slab multi-GPU "
