@@ -28,6 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                       # MI355X HBM3E
+# The step kernel's duration comes from HIP events on one timed launch in
+# PROFILE_EVERY (every launch is the same work); recording events costs a few
+# microseconds per launch, which would otherwise land in ms_per_step.
+PROFILE_EVERY = 8
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2205_02774_amd", "csrc", f) for f in ("lattice_step.h", "lattice_kernels.hip")]
 
@@ -84,7 +88,7 @@ def run_variant(cfg, store, steps, warmup, stats=True, velocity_set=19, collisio
     log(f"[bench] {cfg['name']} {store}: setup + {warmup} warm-up steps in {time.perf_counter() - t0:.1f} s")
     if stats:
         lat.stats_reset()
-    lat.profile(True)
+    lat.profile(True, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     lat.step(steps)
@@ -156,7 +160,7 @@ def periodic_reference(nx, ny, nz, steps, warmup):
     lat.step(warmup)
     lat.sync()
     lat.stats_reset()
-    lat.profile(True)
+    lat.profile(True, every=PROFILE_EVERY)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     lat.step(steps)

@@ -233,9 +233,12 @@ int stglbm_checkpoint(stglbm_t h, void* h_buf, uint64_t n);
 int stglbm_restore(stglbm_t h, const void* h_buf, uint64_t n);
 
 /* Timing of the fused step kernel and the STG kernel with HIP events on the
- * handle's stream while enabled.  out[5] = {step-kernel ms total, launches,
- * STG-kernel ms total, inlet planes generated, STG launches}; reading
- * synchronizes and clears.  n >= 5. */
+ * handle's stream.  enable = 0: off; enable = k >= 1: every STG launch and
+ * every k-th step-kernel launch (the first after this call, then one in k),
+ * so that the events' own cost (a few us per recorded launch) stays off most
+ * steps.  out[5] = {timed step-kernel ms total, timed step launches, STG-kernel
+ * ms total, inlet planes generated, STG launches}; reading synchronizes and
+ * clears.  n >= 5.  E_INVAL if enable < 0. */
 int stglbm_profile(stglbm_t h, int32_t enable);
 int stglbm_profile_read(stglbm_t h, double* out, uint64_t n);
 

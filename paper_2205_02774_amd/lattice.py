@@ -238,8 +238,9 @@ class Lattice:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         self._chk(self.lib.stglbm_restore(self.handle, ctypes.c_void_p(buf.ctypes.data), buf.size))
 
-    def profile(self, enable=True):
-        self._chk(self.lib.stglbm_profile(self.handle, 1 if enable else 0))
+    def profile(self, enable=True, every=1):
+        """Time the step kernel (one launch in `every`) and every STG launch with HIP events."""
+        self._chk(self.lib.stglbm_profile(self.handle, int(every) if enable else 0))
 
     def profile_read(self):
         """{'step_ms', 'step_launches', 'stg_ms', 'stg_planes', 'stg_launches'} since the last read."""

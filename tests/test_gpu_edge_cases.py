@@ -82,3 +82,26 @@ def test_zero_steps_is_a_no_op():
     lat.step(0)
     np.testing.assert_array_equal(lat.get_f(), f0)
     lat.close()
+
+
+def test_profile_times_one_launch_in_every():
+    """stglbm_profile(k): every STG launch and the step kernel on steps 0, k, 2k, ... after the call."""
+    from paper_2205_02774_amd import abi, channel_from_config
+    cfg = small_channel(24, 16, 8, n_modes=10, seed=3)
+    lat = channel_from_config(cfg, device="cuda:0")
+    lat.profile(True, every=4)
+    lat.step(10)
+    pr = lat.profile_read()
+    assert pr["step_launches"] == 3 and pr["stg_launches"] == 2 and pr["stg_planes"] == 16
+    assert pr["step_ms"] > 0.0 and pr["stg_ms"] > 0.0
+    lat.profile(True)
+    lat.step(5)
+    pr = lat.profile_read()
+    assert pr["step_launches"] == 5
+    lat.profile(False)
+    lat.step(2)
+    assert lat.profile_read()["step_launches"] == 0
+    with pytest.raises(abi.StglbmError) as e:
+        lat._chk(lat.lib.stglbm_profile(lat.handle, -1))
+    assert e.value.code == abi.E_INVAL
+    lat.close()
