@@ -9,6 +9,7 @@
 
 #include "stglbm_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -123,18 +124,26 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   L.nxg = (L.nxt + wx - 1) / wx;
   const int base = L.nxg * d->ny;
   if (lw == 0) {
+    // 8 blocks share each (x, y) bin (8 FP64 slots), more where the grid
+    // would otherwise hold fewer than 8192 waves.  Measured on MI355X:
+    // 512x128x256 FP32 0.526 ms (16 slots: 0.533), FP16 0.3055 ms (16 slots:
+    // 0.3079); 1024x256x512 FP16 2.219 ms (4 slots: 2.277).
     const int zmax = (d->nz + wz - 1) / wz;
-    int slots = (2048 + base - 1) / base;
-    if (slots < 1) slots = 1;
+    const int waves = base * wx * wz;
+    int slots = (8192 + waves - 1) / waves;
+    if (slots < 8) slots = 8;
     if (slots > zmax) slots = zmax;
     lw = (d->nz + wz * slots - 1) / (wz * slots);
   }
   L.lw = lw;
-  // Without statistics the z chunk only sets the block size; measured on
-  // MI355X, blocks streaming about 2 KB of each population row are fastest
-  // (one FP32 row of 512 cells, two FP16 rows).
-  const int row_bytes = d->nx * store_bytes(d->store);
-  L.lw_idle = row_bytes >= 2048 ? 1 : (2048 + row_bytes - 1) / row_bytes;
+  // Without statistics the z chunk only sets the block size.  Measured on
+  // MI355X, the fastest blocks stream about 2 KB of each population row for
+  // FP32 (one z row of 512 cells: 0.477 ms; two: 0.481) and about 4 KB for
+  // 16-bit stores (512x128x256: 4 rows 0.268 ms, 2 rows 0.271, 1 row 0.303;
+  // 1024x256x512 in half-row blocks: 4 rows 2.10 ms, 2 rows 2.17, 1 row 2.39).
+  const int block_row_bytes = std::min(d->nx, L.wx_idle * 64 * vec) * store_bytes(d->store);
+  const int target = d->store == STGLBM_F32 ? 2048 : 4096;
+  L.lw_idle = std::max(1, (target + block_row_bytes - 1) / block_row_bytes);
   L.nxg_idle = (L.nxt + L.wx_idle - 1) / L.wx_idle;
   L.slots = (d->nz + wz * lw - 1) / (wz * lw);
   L.zstep = interleave ? L.slots * wz : wz;
