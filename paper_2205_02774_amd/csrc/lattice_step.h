@@ -583,9 +583,22 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
   }
 
   if (STATS) {
-    // per-(x, y) sums over the block's z range: registers, then the wz waves in LDS
+    // per-(x, y) sums over the block's z range: registers, then the wz waves in
+    // LDS.  All 9 slot values are loaded first, before the barrier: a
+    // read-modify-write per quantity would make 9 dependent round trips (the
+    // stores may alias the later loads as far as the compiler knows).
     extern __shared__ float red[];             // [wz][9][64 wx V]
     const int tx = threadIdx.x, bx = 64 * p.wx * V;
+    const bool rmw = wz == 0 && active && wave_live;
+    const long long sstride = (long long)ny * nx;
+    double* st = p.stats + (long long)slot * 9 * sstride + (long long)y * nx + x0;
+    double old[9][V];
+    if (rmw) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q)
+#pragma unroll
+        for (int k = 0; k < V; ++k) old[q][k] = st[q * sstride + k];
+    }
     if (p.wz > 1) {
 #pragma unroll
       for (int q = 0; q < 9; ++q)
@@ -593,16 +606,14 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
         for (int k = 0; k < V; ++k) red[(wz * 9 + q) * bx + tx * V + k] = acc[q][k];
       __syncthreads();
     }
-    if (wz == 0 && active && wave_live) {
-      const long long sstride = (long long)ny * nx;
-      double* st = p.stats + (long long)slot * 9 * sstride + (long long)y * nx + x0;
+    if (rmw) {
 #pragma unroll
       for (int q = 0; q < 9; ++q)
 #pragma unroll
         for (int k = 0; k < V; ++k) {
           float v = acc[q][k];
           for (int w = 1; w < p.wz; ++w) v += red[(w * 9 + q) * bx + tx * V + k];
-          st[q * sstride + k] += static_cast<double>(v);
+          st[q * sstride + k] = old[q][k] + static_cast<double>(v);
         }
     }
   }
