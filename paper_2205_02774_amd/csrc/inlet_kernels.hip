@@ -236,11 +236,15 @@ __global__ __launch_bounds__(64 * kStgWaves) void stg_plane_kernel(StgParams p) 
   const int z = blockIdx.x * 64 + lane;
   const double tphase = p.tphase[blockIdx.z];
   const int zc = z < p.nz ? z : p.nz - 1;
-  // modes staged per pass (LDS stays under 64 KiB per block)
-  constexpr int kChunk = kStgRows >= 4 ? kStgChunk / 2 : kStgChunk;
-  __shared__ float2 P[kStgRows][kChunk];
-  __shared__ float4 SG[kChunk];
-  __shared__ float red[kStgWaves][3 * kStgRows][64];
+  // Modes staged per pass; the row phasors and sigma of the last pass are dead
+  // when the partial sums meet, so the two share LDS (under 64 KiB per block).
+  constexpr int kChunk = kStgChunk * 2 / (kStgRows >= 2 ? kStgRows : 2);
+  constexpr int kStageBytes = kStgRows * kChunk * 8 + kChunk * 16;
+  constexpr int kRedBytes = kStgWaves * 3 * kStgRows * 64 * 4;
+  __shared__ __attribute__((aligned(16))) char smem[kStageBytes > kRedBytes ? kStageBytes : kRedBytes];
+  float2 (*P)[kChunk] = reinterpret_cast<float2 (*)[kChunk]>(smem);
+  float4* SG = reinterpret_cast<float4*>(smem + kStgRows * kChunk * 8);
+  float (*red)[3 * kStgRows][64] = reinterpret_cast<float (*)[3 * kStgRows][64]>(smem);
   const double sqrt6 = 2.449489742783178098;
   float v[kStgRows][3];
 #pragma unroll
@@ -347,18 +351,19 @@ hipError_t launch_stg(const StgParams& p, hipStream_t s) {
   const dim3 block(64, kStgWaves);
   const long long zb = (p.nz + 63) / 64;
   if (p.n_planes < 1 || p.n_planes > kStgBatch) return hipErrorInvalidValue;
-  int rows = 4;
+  int rows = 8;
   while (rows > 1 && zb * ((p.ny + rows - 1) / rows) * p.n_planes * kStgWaves < 2048) rows /= 2;
-  if (const char* env = std::getenv("STGLBM_STG_ROWS")) {   // tuning override: 1, 2 or 4
+  if (const char* env = std::getenv("STGLBM_STG_ROWS")) {   // tuning override: 1, 2, 4 or 8
     const int r = std::atoi(env);
-    if (r == 1 || r == 2 || r == 4) rows = r;
+    if (r == 1 || r == 2 || r == 4 || r == 8) rows = r;
   }
   const dim3 grid(static_cast<unsigned>(zb), static_cast<unsigned>((p.ny + rows - 1) / rows),
                   static_cast<unsigned>(p.n_planes));
   switch (rows) {
     case 1: stg_plane_kernel<1><<<grid, block, 0, s>>>(p); break;
     case 2: stg_plane_kernel<2><<<grid, block, 0, s>>>(p); break;
-    default: stg_plane_kernel<4><<<grid, block, 0, s>>>(p); break;
+    case 4: stg_plane_kernel<4><<<grid, block, 0, s>>>(p); break;
+    default: stg_plane_kernel<8><<<grid, block, 0, s>>>(p); break;
   }
   return hipGetLastError();
 }

@@ -10,7 +10,7 @@ constexpr int kRowFields = 18;      // U(3) k omega R(6) a(6) l_e
 constexpr int kModeFields = 8;      // k, d(3), sigma(3), phi
 constexpr int kScalars = 8;         // L_e k_min k_max alpha k_cut clamps U_b N
 constexpr int kMaxWavesPerBlock = 8; // step kernel: waves along x times waves along z
-constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel (half for 4-row blocks)
+constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel (2048 / rows for 4 and 8 rows)
 constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
 constexpr int kStgBatch = 8;        // inlet planes generated per STG launch during stepping
 
