@@ -174,7 +174,8 @@ int stglbm_get_stats(stglbm_t h, double* h_out, uint64_t n, int64_t* n_samples);
  * Uses the inactive buffer as staging. n = Q*NX*NY*NZ. */
 int stglbm_get_f(stglbm_t h, double* h_out, uint64_t n);
 /* f = w + g for the planes x0 <= x < x1 only, FP64 [Q][NZ][NY][x1-x0];
- * synchronizes. n = Q*NZ*NY*(x1-x0). */
+ * synchronizes; staged through the inactive buffer in pieces like get_f.
+ * n = Q*NZ*NY*(x1-x0). */
 int stglbm_get_f_planes(stglbm_t h, int32_t x0, int32_t x1, double* h_out, uint64_t n);
 /* Device address and size in bytes of the current distributions g (store
  * type, device layout [NZ][Q][NY][NX]); valid until the next step or

@@ -630,13 +630,18 @@ int stglbm_get_f_planes(stglbm_t h, int32_t x0, int32_t x1, double* h_out, uint6
   if (x0 < 0 || x1 > h->d.nx || x1 <= x0) return fail(h, STGLBM_E_INVAL, "need 0 <= x0 < x1 <= NX");
   const uint64_t total = static_cast<uint64_t>(h->q()) * h->d.nz * h->d.ny * (x1 - x0);
   if (!h_out || n != total) return fail(h, STGLBM_E_INVAL, "buffer must hold Q*NZ*NY*(x1-x0) doubles");
-  if (total * sizeof(double) > h->gbytes()) return fail(h, STGLBM_E_INVAL, "plane range larger than the staging buffer");
   const int rc = sync_and_check(h);
   double* stage = static_cast<double*>(h->gbuf(1 - h->cur));
-  HIP_CHECK(h, launch_export_planes(h->gbuf(h->cur), h->d.store, h->q(), h->d.nx, h->d.ny, h->d.nz, x0, x1, stage, h->stream),
-            "export kernel");
-  HIP_CHECK(h, hipMemcpyAsync(h_out, stage, total * sizeof(double), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync f");
-  HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  const uint64_t chunk = h->gbytes() / sizeof(double);   // the inactive buffer stages one chunk at a time
+  for (uint64_t off = 0; off < total; off += chunk) {
+    const uint64_t cnt = std::min<uint64_t>(chunk, total - off);
+    HIP_CHECK(h, launch_export_planes(h->gbuf(h->cur), h->d.store, h->q(), h->d.nx, h->d.ny, h->d.nz, x0, x1,
+                                      static_cast<long long>(off), static_cast<long long>(cnt), stage, h->stream),
+              "export kernel");
+    HIP_CHECK(h, hipMemcpyAsync(h_out + off, stage, cnt * sizeof(double), hipMemcpyDeviceToHost, h->stream),
+              "hipMemcpyAsync f");
+    HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+  }
   return rc;
 }
 

@@ -70,13 +70,13 @@ __global__ void export_f_kernel(const typename Codec::storage* g, long long offs
 
 template <class Codec, int QN>
 __global__ void export_planes_kernel(const typename Codec::storage* g, int nx, int ny, int nz, int x0, int w,
-                                     double* out) {
-  const long long count = (long long)QN * nz * ny * w;
+                                     long long offset, long long count, double* out) {
   const long long plane2d = (long long)nx * ny;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += stride) {
-    const int xx = static_cast<int>(k % w);
-    const long long r = k / w;                    // (i, z, y)
+    const long long e = offset + k;               // element of [Q][NZ][NY][w]
+    const int xx = static_cast<int>(e % w);
+    const long long r = e / w;                    // (i, z, y)
     const int i = static_cast<int>(r / ((long long)nz * ny));
     const long long zy = r % ((long long)nz * ny);
     const long long z = zy / ny, y = zy % ny;
@@ -219,13 +219,13 @@ hipError_t launch_export_f(const void* g, int store, int q, long long offset, lo
 }
 
 hipError_t launch_export_planes(const void* g, int store, int q, int nx, int ny, int nz, int x0, int x1,
-                                double* out, hipStream_t s) {
+                                long long offset, long long count, double* out, hipStream_t s) {
   const int w = x1 - x0;
-  const int grid = grid_for(static_cast<unsigned long long>(q) * nz * ny * w, 256);
+  const int grid = grid_for(static_cast<unsigned long long>(count), 256);
   return by_store_and_set(store, q, [&](auto codec, auto qn) {
     using C = decltype(codec);
     export_planes_kernel<C, decltype(qn)::value><<<grid, 256, 0, s>>>(static_cast<const typename C::storage*>(g),
-                                                                       nx, ny, nz, x0, w, out);
+                                                                       nx, ny, nz, x0, w, offset, count, out);
     return hipGetLastError();
   });
 }

@@ -101,7 +101,7 @@ hipError_t launch_sponge(float* sponge, int nx, int cells, double K, double p, h
 hipError_t launch_export_f(const void* g, int store, int q, long long offset, long long count, int nz,
                            long long plane2d, double* out, hipStream_t s);
 hipError_t launch_export_planes(const void* g, int store, int q, int nx, int ny, int nz, int x0, int x1,
-                                double* out, hipStream_t s);
+                                long long offset, long long count, double* out, hipStream_t s);
 hipError_t launch_import_f(const double* f, int store, int q, long long offset, long long count, int nz,
                            long long plane2d, void* g, hipStream_t s);
 hipError_t launch_equilibrium(const double* u, int store, int q, int nx, int ny, int nz, void* g, hipStream_t s);

@@ -117,3 +117,27 @@ def test_half_store_variant_channel(q, store, unit):
     print(f"[gpu] D3Q{q} {store}: max rel err after {K} steps {rel.max():.3e}, bound {bound:.3e}", flush=True)
     assert rel.max() < bound
     lat.close()
+
+
+@pytest.mark.parametrize("q", [15, 27])
+@pytest.mark.parametrize("store,unit,floor", [("f32", 2.0 ** -24, 0.0), ("f16", 2.0 ** -11, 2.0 ** -25)])
+def test_equilibrium_import_and_plane_export(q, store, unit, floor):
+    """set_equilibrium gives f_eq(1, u) of the velocity set rounded once to the
+    store; get_f_planes returns exactly those planes of get_f."""
+    from paper_2205_02774_amd import Lattice
+    nx, ny, nz = 20, 6, 3
+    rng = np.random.default_rng(q)
+    u = rng.uniform(-0.08, 0.08, size=(3, nz, ny, nx))
+    ref = OL.equilibrium(np.ones((nz, ny, nx)), u, q=q)
+    print(f"[gpu] variant D3Q{q} {store}: equilibrium import, plane export", flush=True)
+    lat = Lattice(nx, ny, nz, device="cuda:0", store=store, periodic_x=True, nu_lb=1e-2, velocity_set=q)
+    lat.set_equilibrium(u)
+    f = lat.get_f()
+    planes = lat.get_f_planes(3, 9)
+    whole = lat.get_f_planes(0, nx)              # 16-bit stores: 4 pieces through the staging buffer
+    lat.close()
+    W = OL.velocity_set(q).W[:, None, None, None]
+    bound = (unit + 2.0 ** -24) * np.abs(ref - W) + floor + 1e-15
+    assert np.all(np.abs(f - ref) <= bound)
+    np.testing.assert_array_equal(planes, f[..., 3:9])
+    np.testing.assert_array_equal(whole, f)
