@@ -5,7 +5,8 @@ computes, written from the paper (Xue, Yao & Davidson, "Synthetic turbulence
 generator for lattice Boltzmann method at the interface between RANS and
 LES"), section by section:
 
-* ``lattice``  -- D3Q19 lattice BGK with Guo forcing (Methodology, eqs.
+* ``lattice``  -- D3Q19 (and D3Q15, D3Q27) lattice BGK, regularized or
+  plain, with Guo forcing (Methodology, eqs.
   density/momentum/tensor, lbe, local_eq, lbe-nu, bodyforce), Smagorinsky
   effective relaxation (eqs. smogrinsky_model, strain, tau_eff), regularized
   boundary reconstruction (eqs. f_i .. bc_eq), halfway bounce-back walls,
