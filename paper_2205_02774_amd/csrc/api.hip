@@ -92,7 +92,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   int wx = 0;
   int wz = 1;
   int lw = 0;
-  int interleave = 1;
+  int interleave = 0;
   if (const char* env = std::getenv("STGLBM_SHAPE")) {   // "wx,wz,lw[,vec[,interleave]]" tuning override
     int a = 0, b = 0, c = 0, v = 0, il = 1;
     const int n = std::sscanf(env, "%d,%d,%d,%d,%d", &a, &b, &c, &v, &il);
@@ -108,26 +108,17 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   L.nxt = (d->nx + 64 * vec - 1) / (64 * vec);
   const int wx_row = L.nxt < 8 ? L.nxt : 8;   // whole rows of up to 8 tiles
   L.wx_idle = wx == 0 ? wx_row : wx;
-  if (wx == 0) {
-    // Steps that sample statistics: for FP32, half rows with two z waves per
-    // block halve the FP64 slots at the same block count (measured 0.535 ->
-    // 0.528 ms on 512x128x256); 16-bit stores keep whole rows (0.309 vs 0.322 ms).
-    if (d->store == STGLBM_F32 && wx_row >= 2) {
-      wx = wx_row / 2;
-      wz = 2;
-    } else {
-      wx = wx_row;
-    }
-  }
+  if (wx == 0) wx = wx_row;   // whole rows of up to 8 tiles, one z wave, for both launch kinds
   L.wx = wx;
   L.wz = wz;
   L.nxg = (L.nxt + wx - 1) / wx;
   const int base = L.nxg * d->ny;
   if (lw == 0) {
-    // 8 blocks share each (x, y) bin (8 FP64 slots), more where the grid
-    // would otherwise hold fewer than 8192 waves.  Measured on MI355X:
-    // 512x128x256 FP32 0.526 ms (16 slots: 0.533), FP16 0.3055 ms (16 slots:
-    // 0.3079); 1024x256x512 FP16 2.219 ms (4 slots: 2.277).
+    // 8 blocks share each (x, y) bin (8 FP64 slots), each taking one
+    // contiguous z chunk; more where the grid would otherwise hold fewer than
+    // 8192 waves.  Measured on MI355X: 512x128x256 FP32 0.504 ms (16 slots:
+    // 0.510; half rows with two z waves: 0.511; z chunks interleaved over the
+    // blocks: 0.516), FP16 0.296 ms; 1024x256x512 FP16 2.21 ms (4 slots: 2.28).
     const int zmax = (d->nz + wz - 1) / wz;
     const int waves = base * wx * wz;
     int slots = (8192 + waves - 1) / waves;
@@ -295,7 +286,10 @@ StepParams step_params(stglbm_t h) {
     p.zstep = 1;
     p.nblocks = p.nxg * d.ny * p.slots;
   }
-  p.remap = (p.nblocks % 8 == 0) ? 1 : 0;
+  // One block per row (nxg = 1): the hardware's turn-by-turn XCD order is
+  // kept (a contiguous range per XCD measured 3 % slower on 512x128x256).
+  p.remap = (p.nxg > 1 && p.nblocks % (8 * p.nxg) == 0) ? 1 : 0;
+  if (const char* env = std::getenv("STGLBM_REMAP")) p.remap = std::atoi(env) && p.nxg > 1 && p.nblocks % (8 * p.nxg) == 0;
   p.periodic_x = d.periodic_x;
   p.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
   const double tau0 = 0.5 + 3.0 * d.nu_lb;

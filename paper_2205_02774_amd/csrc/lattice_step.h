@@ -255,8 +255,12 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
   const int wz = __builtin_amdgcn_readfirstlane(threadIdx.y);
   int b = blockIdx.x;
   if (p.remap) {
-    const int per = p.nblocks >> 3;
-    b = (b & 7) * per + (b >> 3);
+    // Workgroups go to the 8 XCDs in turn (blockIdx.x mod 8).  When a row
+    // spans several blocks (nxg > 1), give the nxg blocks of a row to one XCD,
+    // so the lines that the +-1 x shifts share stay in one L2, while
+    // consecutive rows still rotate over the XCDs.
+    const int xcd = b & 7, k = b >> 3;
+    b = ((k / p.nxg) * 8 + xcd) * p.nxg + k % p.nxg;
   }
   const int xg = b % p.nxg;
   const int rest = b / p.nxg;
