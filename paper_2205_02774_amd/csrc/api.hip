@@ -114,15 +114,20 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   L.nxg = (L.nxt + wx - 1) / wx;
   const int base = L.nxg * d->ny;
   if (lw == 0) {
-    // 8 blocks share each (x, y) bin (8 FP64 slots), each taking one
-    // contiguous z chunk; more where the grid would otherwise hold fewer than
-    // 8192 waves.  Measured on MI355X: 512x128x256 FP32 0.504 ms (16 slots:
-    // 0.510; half rows with two z waves: 0.511; z chunks interleaved over the
-    // blocks: 0.516), FP16 0.296 ms; 1024x256x512 FP16 2.21 ms (4 slots: 2.28).
+    // Each block takes one contiguous z chunk; the blocks sharing an (x, y)
+    // bin are its FP64 slots.  FP32 (waves kept in step): 4 slots, more where
+    // the grid would hold fewer than 4096 waves; 16-bit stores: 16 slots and
+    // 8192 waves.  Measured on MI355X, 512x128x256: FP32 0.476 ms (8 slots:
+    // 0.482, 16: 0.494; half rows with two z waves or z chunks interleaved
+    // over the blocks: 1-3 % slower); FP16 0.293 ms (8 slots: 0.296), BF16
+    // 0.297 (0.303); 1024x256x512 FP16: 16 slots within 0.3 % of 8, 4 slots
+    // 3 % slower.
+    const bool f32 = d->store == STGLBM_F32;
     const int zmax = (d->nz + wz - 1) / wz;
     const int waves = base * wx * wz;
-    int slots = (8192 + waves - 1) / waves;
-    if (slots < 8) slots = 8;
+    const int min_waves = f32 ? 4096 : 8192, min_slots = f32 ? 4 : 16;
+    int slots = (min_waves + waves - 1) / waves;
+    if (slots < min_slots) slots = min_slots;
     if (slots > zmax) slots = zmax;
     lw = (d->nz + wz * slots - 1) / (wz * slots);
   }
@@ -290,6 +295,10 @@ StepParams step_params(stglbm_t h) {
   // kept (a contiguous range per XCD measured 3 % slower on 512x128x256).
   p.remap = (p.nxg > 1 && p.nblocks % (8 * p.nxg) == 0) ? 1 : 0;
   if (const char* env = std::getenv("STGLBM_REMAP")) p.remap = std::atoi(env) && p.nxg > 1 && p.nblocks % (8 * p.nxg) == 0;
+  // FP32 statistics launches keep their waves in step (512x128x256: 0.505 ->
+  // 0.499 ms); 16-bit rows are one cache line per wave and lost 5 % with it.
+  p.lockstep = d.store == STGLBM_F32 ? 1 : 0;
+  if (const char* env = std::getenv("STGLBM_LOCKSTEP")) p.lockstep = std::atoi(env) ? 1 : 0;
   p.periodic_x = d.periodic_x;
   p.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
   const double tau0 = 0.5 + 3.0 * d.nu_lb;

@@ -318,13 +318,50 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
   // the blocks resident at a time cover one contiguous band of z per
   // population plane; zstep = wz gives each block a contiguous z chunk.
   const int z0 = slot * p.wz * (p.zstep == p.wz ? p.lw : 1) + wz;
-  // FP32 statistics launches with one z wave per block keep the block's
-  // waves in step (a barrier per z row), so neighbouring waves read the cache
-  // lines they share while both are in L2 (512x128x256: 0.505 -> 0.499 ms;
-  // the same for 16-bit stores, whose rows are one line per wave, lost 5 %).
-  // Every wave of such a block makes the same trips: z depends only on the
-  // block, and the waves past the last x tile go round the loop too.
-  const bool lockstep = STATS && SB == 4 && p.wz == 1;
+  // Statistics launches with one z wave per block may keep the block's waves
+  // in step (a barrier per z row, p.lockstep), so neighbouring waves read the
+  // cache lines they share while both are in L2.  Every wave of such a block
+  // makes the same trips: z depends only on the block, and the waves past the
+  // last x tile go round the loop too.
+  const bool lockstep = STATS && p.lockstep && p.wz == 1;
+  // Source rows depend on y only: population, row and bounce-back choice.
+  const unsigned row_here = static_cast<unsigned>(y * nx) * SB;
+  unsigned so[QN];
+  bool wall[QN];
+#pragma unroll
+  for (int i = 0; i < QN; ++i) {
+    const int ys = y - vcy<QN>(i);
+    wall[i] = ys < 0 || ys >= ny;                       // uniform over the block
+    const int pop = wall[i] ? vopp(i) : i;
+    const unsigned row = wall[i] ? row_here : static_cast<unsigned>(ys * nx) * SB;
+    // uniform by construction; readfirstlane keeps it in a scalar register
+    // (a vector copy would make the compiler loop over lanes for the load)
+    so[i] = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(pop) * pop_bytes + row);
+  }
+  // pull streaming: g_i(x) <- g_i(x - c_i); bounce-back g_opp(i)(x) behind a wall
+  unsigned w[QN][NW];
+  auto load_row = [&](int zz) {
+    const int zzm = zz == 0 ? nz - 1 : zz - 1;
+    const int zzp = zz == nz - 1 ? 0 : zz + 1;
+    const __amdgpu_buffer_rsrc_t r3[3] = {
+        __builtin_amdgcn_make_buffer_rsrc(gin + zzm * slice, (short)0, slice_bytes, kBufferWord3),
+        __builtin_amdgcn_make_buffer_rsrc(gin + zz * slice, (short)0, slice_bytes, kBufferWord3),
+        __builtin_amdgcn_make_buffer_rsrc(gin + zzp * slice, (short)0, slice_bytes, kBufferWord3)};
+#pragma unroll
+    for (int i = 0; i < QN; ++i) {
+      const __amdgpu_buffer_rsrc_t r = wall[i] ? r3[1] : r3[1 - vcz<QN>(i)];
+      // one cell per lane: load the source cell x - c_x directly
+      const unsigned voff = (V > 1 || wall[i] || vcx<QN>(i) == 0) ? v_here : (vcx<QN>(i) > 0 ? v_m : v_p);
+      Vec::load(r, voff, so[i], w[i]);
+    }
+  };
+  // In FP32 statistics launches (several z rows per wave, one cell per lane)
+  // the next row's loads are issued after this row's arithmetic and before
+  // its stores, so waiting for them does not wait for the stores (the memory
+  // counter is in order): 512x128x256 0.498 -> 0.481 ms.  The 16-bit launches
+  // measured no gain (BF16 a loss) and keep the loads at the top of the loop.
+  constexpr bool kPipe = STATS && V == 1 && SB == 4;
+  if (kPipe && wave_live && z0 < nz && p.lw > 0) load_row(z0);
   for (int it = 0; it < ((wave_live || lockstep) ? p.lw : 0); ++it) {
     const int z = z0 + it * p.zstep;
     if (z >= nz) break;
@@ -334,7 +371,6 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
     }
     const int zm = z == 0 ? nz - 1 : z - 1;
     const int zp = z == nz - 1 ? 0 : z + 1;
-    const unsigned row_here = static_cast<unsigned>(y * nx) * SB;
     // source slices z - c_z for c_z = +1, 0, -1, and the destination slice
     const __amdgpu_buffer_rsrc_t rin[3] = {
         __builtin_amdgcn_make_buffer_rsrc(gin + zm * slice, (short)0, slice_bytes, kBufferWord3),
@@ -342,25 +378,7 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
         __builtin_amdgcn_make_buffer_rsrc(gin + zp * slice, (short)0, slice_bytes, kBufferWord3)};
     const __amdgpu_buffer_rsrc_t rout =
         __builtin_amdgcn_make_buffer_rsrc(gout + z * slice, (short)0, slice_bytes, kBufferWord3);
-
-    // pull streaming: g_i(x) <- g_i(x - c_i); bounce-back g_opp(i)(x) behind a wall
-    unsigned w[QN][NW];
-    unsigned so[QN];
-    bool wall[QN];
-#pragma unroll
-    for (int i = 0; i < QN; ++i) {
-      const int ys = y - vcy<QN>(i);
-      wall[i] = ys < 0 || ys >= ny;                     // uniform over the block
-      const int pop = wall[i] ? vopp(i) : i;
-      const unsigned row = wall[i] ? row_here : static_cast<unsigned>(ys * nx) * SB;
-      // uniform by construction; readfirstlane keeps it in a scalar register
-      // (a vector copy would make the compiler loop over lanes for the load)
-      so[i] = __builtin_amdgcn_readfirstlane(static_cast<unsigned>(pop) * pop_bytes + row);
-      const __amdgpu_buffer_rsrc_t r = wall[i] ? rin[1] : rin[1 - vcz<QN>(i)];
-      // one cell per lane: load the source cell x - c_x directly
-      const unsigned voff = (V > 1 || wall[i] || vcx<QN>(i) == 0) ? v_here : (vcx<QN>(i) > 0 ? v_m : v_p);
-      Vec::load(r, voff, so[i], w[i]);
-    }
+    if (!kPipe) load_row(z);
     // cross-lane elements of the x-moving populations (bounce-back ones stay put)
     unsigned ext[QN];
 #pragma unroll
@@ -582,6 +600,7 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
       }
     }
 
+    if (kPipe && it + 1 < p.lw && z + p.zstep < nz) load_row(z + p.zstep);
     if (active) {
 #pragma unroll
       for (int i = 0; i < QN; ++i)

@@ -35,6 +35,7 @@ struct StepParams {
   int zstep;                // z distance between a wave's rows: slots * wz (interleaved) or wz (chunked)
   int nblocks;
   int remap;                // 1: the blocks of a row share an XCD (nxg > 1, nblocks % (8 nxg) == 0)
+  int lockstep;             // statistics launches with wz = 1: a barrier per z row
   int periodic_x;
   int has_force;
   float tau0, tau0_sq;      // tau0 and tau0^2 (rounded from FP64)
