@@ -105,3 +105,36 @@ def test_profile_times_one_launch_in_every():
         lat._chk(lat.lib.stglbm_profile(lat.handle, -1))
     assert e.value.code == abi.E_INVAL
     lat.close()
+
+
+@pytest.mark.parametrize("store", ["f32", "f16"])
+def test_rows_wider_than_one_block_with_idle_waves(store):
+    """NX = 581: 10 tiles of 64, whole-row blocks of 8 waves, so the second
+    block of each row has 2 working waves and 6 that only keep step with
+    them (FP32 statistics launches hold a barrier per z row)."""
+    from paper_2205_02774_amd import Lattice
+    from oracle.lattice import W
+    nx, ny, nz = 581, 4, 6
+    nu, cs, force = 2e-2, 0.1, (1e-5, 0.0, 0.0)
+    print(f"[gpu] edge wide rows {store}", flush=True)
+    lat = Lattice(nx, ny, nz, device="cuda:0", store=store, periodic_x=True, nu_lb=nu, cs_smag=cs, force=force)
+    ora = OracleChannel(nx, ny, nz, nu_lb=nu, cs_smag=cs, force=force, periodic_x=True)
+    rng = np.random.default_rng(11)
+    lat.set_f(W[:, None, None, None] * (1.0 + 1e-2 * rng.uniform(-1, 1, (19, nz, ny, nx))))
+    ora.set_f(lat.get_f())
+    lat.stats_reset()
+    ora.stats_reset()
+    lat.step(30)
+    ora.step(30)
+    st, n = lat.get_stats()
+    f = lat.get_f()
+    lat.close()
+    rel = _rel(f, ora.f)
+    nrm = np.linalg.norm(st - ora.stats) / np.linalg.norm(ora.stats)
+    print(f"[gpu] edge wide rows {store}: max rel err f {rel.max():.3e}, stats {nrm:.3e}", flush=True)
+    assert n == 30
+    if store == "f32":
+        assert rel.max() < 1e-6 and nrm < 1e-6
+    else:
+        # 16-bit store: every step rounds g to 2^-11 relative; |g/f| <= 1e-2 here
+        assert rel.max() < 4 * np.sqrt(30) * 2.0 ** -11 * 2e-2 and nrm < 1e-3
