@@ -15,8 +15,9 @@
 // row part k^n d^n_y y_j + phi^n + 2 pi d^n_x (x_in - U_b t)/L_e, evaluated in
 // FP64 per (row, mode, step), and a spanwise part k^n d^n_z z held as an FP32
 // phasor.  Their product gives cos of the full phase without a large-argument
-// FP32 cosine.  A block owns one row and 64 spanwise nodes; its 4 waves split
-// the modes, the row phasors and sigma^n are staged in LDS per chunk of modes,
+// FP32 cosine.  A block owns 1 to 8 rows and 64 spanwise nodes of one plane
+// (one launch makes the planes of up to 8 steps); its 8 waves split the
+// modes, the row phasors and sigma^n are staged in LDS per chunk of modes,
 // and the waves' partial sums meet in LDS.
 #include <cstdlib>
 
