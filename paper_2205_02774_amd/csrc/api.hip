@@ -295,9 +295,9 @@ StepParams step_params(stglbm_t h) {
   // kept (a contiguous range per XCD measured 3 % slower on 512x128x256).
   p.remap = (p.nxg > 1 && p.nblocks % (8 * p.nxg) == 0) ? 1 : 0;
   if (const char* env = std::getenv("STGLBM_REMAP")) p.remap = std::atoi(env) && p.nxg > 1 && p.nblocks % (8 * p.nxg) == 0;
-  // FP32 statistics launches keep their waves in step (512x128x256: 0.505 ->
-  // 0.499 ms); 16-bit rows are one cache line per wave and lost 5 % with it.
-  p.lockstep = d.store == STGLBM_F32 ? 1 : 0;
+  // Statistics launches keep their waves in step (512x128x256: FP32 0.505 ->
+  // 0.499 ms, FP16 0.289 -> 0.273 ms).
+  p.lockstep = 1;
   if (const char* env = std::getenv("STGLBM_LOCKSTEP")) p.lockstep = std::atoi(env) ? 1 : 0;
   p.periodic_x = d.periodic_x;
   p.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;

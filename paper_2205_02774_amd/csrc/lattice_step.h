@@ -95,6 +95,15 @@ __device__ __forceinline__ float wmul(int i, float S) {
   return __builtin_fmaf(weight_hi<QN>(i), S, weight_lo<QN>(i) * S);
 }
 
+// w_i * S for the collision outputs: the float-float product with an FP32
+// store, one rounded product with a 16-bit store (whose own rounding is 2^-11
+// or coarser).
+template <int QN, bool EXACT>
+__device__ __forceinline__ float wmul_out(int i, float S) {
+  if constexpr (EXACT) return wmul<QN>(i, S);
+  else return weight_hi<QN>(i) * S;
+}
+
 // Regularized rebuild of a boundary node (eqs. f_i, f_i_neq, pi_neq,
 // unknown_neq, bc_eq): SIGN is the c_x of the unknown (entering) populations.
 // On the known set f_neq = g - g_eq(rho, u); unknown ones mirror their opposite;
@@ -460,33 +469,54 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
         regularized_rebuild<QN, -1>(g, p.rho_out_m1, ux, 0.0f, 0.0f);
       }
 
-      // Moments.  Each g is split into hi (rounded to a multiple of 2^-20, so
-      // integer combinations of hi are exact in FP32 while |sum| < 16) and
-      // lo = g - hi (exact).  Opposite pairs (a, a+1) give exact sums/differences.
+      // Moments.  With an FP32 store each g is split into hi (rounded to a
+      // multiple of 2^-20, so integer combinations of hi are exact in FP32
+      // while |sum| < 16) and lo = g - hi (exact); opposite pairs (a, a+1)
+      // give exact sums and differences.  A 16-bit store rounds g to 2^-11 or
+      // 2^-8 relative every step, far above the rounding of plain FP32 sums,
+      // so those launches sum directly and save about a third of the
+      // arithmetic (they are bound by it, not by HBM).
       constexpr int NP = (QN - 1) / 2;
-      float h[QN], l[QN];
+      constexpr bool kExact = SB == 4;
+      float sg[NP];
+      float dh, dl, jxh, jyh, jzh, jxl, jyl, jzl;
+      if constexpr (kExact) {
+        float h[QN], l[QN];
 #pragma unroll
-      for (int i = 0; i < QN; ++i) {
-        h[i] = (g[i] + kSplit) - kSplit;
-        l[i] = g[i] - h[i];
-      }
-      float sh[NP], dhh[NP], sl[NP], dll[NP], sg[NP];
+        for (int i = 0; i < QN; ++i) {
+          h[i] = (g[i] + kSplit) - kSplit;
+          l[i] = g[i] - h[i];
+        }
+        float sh[NP], dhh[NP], sl[NP], dll[NP];
 #pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        const int a = 2 * q + 1;
-        sh[q] = h[a] + h[a + 1];
-        dhh[q] = h[a] - h[a + 1];
-        sl[q] = l[a] + l[a + 1];
-        dll[q] = l[a] - l[a + 1];
-        sg[q] = g[a] + g[a + 1];
+        for (int q = 0; q < NP; ++q) {
+          const int a = 2 * q + 1;
+          sh[q] = h[a] + h[a + 1];
+          dhh[q] = h[a] - h[a + 1];
+          sl[q] = l[a] + l[a + 1];
+          dll[q] = l[a] - l[a + 1];
+          sg[q] = g[a] + g[a + 1];
+        }
+        dh = h[0] + tree_sum<NP>(sh);
+        dl = l[0] + tree_sum<NP>(sl);
+        // sum c g as hi + lo (each pair contributes c_a (g_a - g_opp))
+        jxh = pair_dot<QN, 0>(dhh); jyh = pair_dot<QN, 1>(dhh); jzh = pair_dot<QN, 2>(dhh);
+        jxl = pair_dot<QN, 0>(dll); jyl = pair_dot<QN, 1>(dll); jzl = pair_dot<QN, 2>(dll);
+      } else {
+        float dg[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const int a = 2 * q + 1;
+          sg[q] = g[a] + g[a + 1];
+          dg[q] = g[a] - g[a + 1];
+        }
+        dh = g[0] + tree_sum<NP>(sg);
+        dl = 0.0f;
+        jxh = pair_dot<QN, 0>(dg); jyh = pair_dot<QN, 1>(dg); jzh = pair_dot<QN, 2>(dg);
+        jxl = jyl = jzl = 0.0f;
       }
-      const float dh = h[0] + tree_sum<NP>(sh);
-      const float dl = l[0] + tree_sum<NP>(sl);
-      // sum c g as hi + lo (each pair contributes c_a (g_a - g_opp))
-      const float jxh = pair_dot<QN, 0>(dhh), jyh = pair_dot<QN, 1>(dhh), jzh = pair_dot<QN, 2>(dhh);
-      const float jxl = pair_dot<QN, 0>(dll), jyl = pair_dot<QN, 1>(dll), jzl = pair_dot<QN, 2>(dll);
       const float drho = dh + dl;
-      const float gsum = g[0] + tree_sum<NP>(sg);
+      const float gsum = kExact ? g[0] + tree_sum<NP>(sg) : dh;
       // sum (3 c_a c_b - delta_ab) g: 3 (pair sums weighted by c_a c_b) - delta_ab sum g
       const float hxx = 3.0f * pair_dot2<QN, 0, 0>(sg) - gsum;
       const float hyy = 3.0f * pair_dot2<QN, 1, 1>(sg) - gsum;
@@ -535,7 +565,7 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
           // rest population: c = 0
           float e0 = base_e + omw45 * (-tr3);
           if (FORCE) e0 += -3.0f * omhw * uF;
-          o[0] = wmul<QN>(0, dh + e0);
+          o[0] = wmul_out<QN, kExact>(0, dh + e0);
         }
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
@@ -552,8 +582,8 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
             E += omhw * (9.0f * cu * cF - 3.0f * uF);
             Ol += cF * (1.5f * (1.0f - omw) + 3.0f * omhw);
           }
-          o[a] = wmul<QN>(a, (dh + Oh) + (E + Ol));
-          o[a + 1] = wmul<QN>(a + 1, (dh - Oh) + (E - Ol));
+          o[a] = wmul_out<QN, kExact>(a, (dh + Oh) + (E + Ol));
+          o[a + 1] = wmul_out<QN, kExact>(a + 1, (dh - Oh) + (E - Ol));
         }
       } else {
         // Plain BGK (eq. lbe): g' = (1 - 1/tau) g + (1/tau) g_eq + Guo source, with
@@ -561,7 +591,7 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
         {
           float e0 = itau * (drho - rho * uu15);
           if (FORCE) e0 += -3.0f * omhw * uF;
-          o[0] = __builtin_fmaf(omw, g[0], wmul<QN>(0, e0));
+          o[0] = __builtin_fmaf(omw, g[0], wmul_out<QN, kExact>(0, e0));
         }
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
@@ -575,8 +605,8 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
             E += omhw * (9.0f * cu * cF - 3.0f * uF);
             O += 3.0f * omhw * cF;
           }
-          o[a] = __builtin_fmaf(omw, g[a], wmul<QN>(a, E + O));
-          o[a + 1] = __builtin_fmaf(omw, g[a + 1], wmul<QN>(a + 1, E - O));
+          o[a] = __builtin_fmaf(omw, g[a], wmul_out<QN, kExact>(a, E + O));
+          o[a + 1] = __builtin_fmaf(omw, g[a + 1], wmul_out<QN, kExact>(a + 1, E - O));
         }
       }
 #pragma unroll
