@@ -87,8 +87,8 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   int vec = 1;
   // Block shape: wx waves along x (consecutive tiles of 64 vec cells of one
   // row) times wz waves along z, each wave stepping lw cells in z.  Default:
-  // whole rows of up to 512 vec cells per block, one wave deep, lw chosen for
-  // >= 2048 blocks.
+  // whole rows of up to 512 vec cells per block, one wave deep (two for the
+  // FP32 statistics launches of D3Q15 / D3Q19), lw as below.
   int wx = 0;
   int wz = 1;
   int lw = 0;
@@ -108,24 +108,31 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   L.nxt = (d->nx + 64 * vec - 1) / (64 * vec);
   const int wx_row = L.nxt < 8 ? L.nxt : 8;   // whole rows of up to 8 tiles
   L.wx_idle = wx == 0 ? wx_row : wx;
-  if (wx == 0) wx = wx_row;   // whole rows of up to 8 tiles, one z wave, for both launch kinds
+  if (wx == 0) wx = wx_row;   // whole rows of up to 8 tiles for both launch kinds
   L.wx = wx;
   L.wz = wz;
   L.nxg = (L.nxt + wx - 1) / wx;
   const int base = L.nxg * d->ny;
   if (lw == 0) {
     // Each block takes one contiguous z chunk; the blocks sharing an (x, y)
-    // bin are its FP64 slots.  FP32 (waves kept in step): 4 slots, more where
-    // the grid would hold fewer than 4096 waves; 16-bit stores: 16 slots and
-    // 8192 waves.  Measured on MI355X, 512x128x256: FP32 0.476 ms (8 slots:
-    // 0.482, 16: 0.494; half rows with two z waves or z chunks interleaved
-    // over the blocks: 1-3 % slower); FP16 0.293 ms (8 slots: 0.296), BF16
-    // 0.297 (0.303); 1024x256x512 FP16: 16 slots within 0.3 % of 8, 4 slots
-    // 3 % slower.
+    // bin are its FP64 slots.  FP32 on D3Q15 / D3Q19 with one cell per lane:
+    // two z waves per block (whole rows, 16 waves: one block fills a CU's
+    // wave slots, so all its waves run in step and finish together), 2 slots,
+    // more where the grid would hold fewer than 4096 waves.  Other FP32 sets:
+    // one z wave, 4 slots.  16-bit stores: one z wave, 16 slots and 8192
+    // waves.  Measured on MI355X, 512x128x256: FP32 0.455 ms (two z waves
+    // and 4 slots 0.457; one z wave: 4 slots 0.476, 8: 0.482, 16: 0.494;
+    // half rows with four z waves 0.477-0.479); with one z wave the two
+    // 8-wave blocks sharing a CU ran at different speeds, and the first to
+    // finish left the CU half empty for the last 10-25 % of the launch.  FP16 0.273 ms (two z waves 0.298), BF16 0.297
+    // (8 slots: 0.303); 1024x256x512 FP16: 16 slots within 0.3 % of 8, 4
+    // slots 3 % slower.
     const bool f32 = d->store == STGLBM_F32;
+    if (L.short_chunks_when_idle && step_max_waves(store_bytes(d->store), set_size(d), vec, true) == kMaxWavesWide) wz = 2;
+    L.wz = wz;
     const int zmax = (d->nz + wz - 1) / wz;
     const int waves = base * wx * wz;
-    const int min_waves = f32 ? 4096 : 8192, min_slots = f32 ? 4 : 16;
+    const int min_waves = f32 ? 4096 : 8192, min_slots = wz == 2 ? 2 : (f32 ? 4 : 16);
     int slots = (min_waves + waves - 1) / waves;
     if (slots < min_slots) slots = min_slots;
     if (slots > zmax) slots = zmax;

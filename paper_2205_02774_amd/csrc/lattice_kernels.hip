@@ -175,7 +175,9 @@ hipError_t by_store_and_set(int store, int q, F&& f) {
 }  // namespace
 
 hipError_t launch_step(const StepParams& p, int store, bool stats, hipStream_t s) {
-  if (p.wx < 1 || p.wz < 1 || p.wx * p.wz > kMaxWavesPerBlock) return hipErrorInvalidValue;
+  if (p.wx < 1 || p.wz < 1) return hipErrorInvalidValue;
+  const int store_bytes = store == 0 ? 4 : 2;
+  if (p.wx * p.wz > step_max_waves(store_bytes, p.q, p.vec, stats)) return hipErrorInvalidValue;
   if (p.vec < 1 || p.nx % p.vec != 0) return hipErrorInvalidValue;
   if (p.q != 19 || p.collision != 0) return launch_step_variant(p, store, stats, s);
   switch (store) {

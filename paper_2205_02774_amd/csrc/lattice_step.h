@@ -252,7 +252,7 @@ __device__ __forceinline__ unsigned from_next_lane(unsigned v) {
 // neighbouring lane by a DPP shift, and only the first and last lanes of a
 // wave load it from memory.
 template <class Codec, int QN, bool REG, int V, bool STATS, bool FORCE>
-__global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams p) {
+__global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage), QN, V, STATS)) void step_kernel(StepParams p) {
   using S = typename Codec::storage;
   constexpr int SB = static_cast<int>(sizeof(S));
   using Vec = Raw<V * SB>;
@@ -327,12 +327,12 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
   // the blocks resident at a time cover one contiguous band of z per
   // population plane; zstep = wz gives each block a contiguous z chunk.
   const int z0 = slot * p.wz * (p.zstep == p.wz ? p.lw : 1) + wz;
-  // Statistics launches with one z wave per block may keep the block's waves
-  // in step (a barrier per z row, p.lockstep), so neighbouring waves read the
-  // cache lines they share while both are in L2.  Every wave of such a block
-  // makes the same trips: z depends only on the block, and the waves past the
-  // last x tile go round the loop too.
-  const bool lockstep = STATS && p.lockstep && p.wz == 1;
+  // Statistics launches may keep the block's waves in step (a barrier per z
+  // row, p.lockstep), so neighbouring waves read the cache lines they share
+  // while both are in L2.  Every wave of such a block makes the same trips:
+  // z - wz depends only on the block, and the waves past the last x tile or
+  // past the last z row go round the loop too.
+  const bool lockstep = STATS && p.lockstep;
   // Source rows depend on y only: population, row and bounce-back choice.
   const unsigned row_here = static_cast<unsigned>(y * nx) * SB;
   unsigned so[QN];
@@ -373,10 +373,12 @@ __global__ __launch_bounds__(64 * kMaxWavesPerBlock) void step_kernel(StepParams
   if (kPipe && wave_live && z0 < nz && p.lw > 0) load_row(z0);
   for (int it = 0; it < ((wave_live || lockstep) ? p.lw : 0); ++it) {
     const int z = z0 + it * p.zstep;
-    if (z >= nz) break;
     if (lockstep) {
+      if (z - wz >= nz) break;
       __syncthreads();
-      if (!wave_live) continue;
+      if (!wave_live || z >= nz) continue;
+    } else if (z >= nz) {
+      break;
     }
     const int zm = z == 0 ? nz - 1 : z - 1;
     const int zp = z == nz - 1 ? 0 : z + 1;

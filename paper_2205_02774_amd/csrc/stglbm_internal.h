@@ -10,6 +10,16 @@ constexpr int kRowFields = 18;      // U(3) k omega R(6) a(6) l_e
 constexpr int kModeFields = 8;      // k, d(3), sigma(3), phi
 constexpr int kScalars = 8;         // L_e k_min k_max alpha k_cut clamps U_b N
 constexpr int kMaxWavesPerBlock = 8; // step kernel: waves along x times waves along z
+constexpr int kMaxWavesWide = 16;    // FP32 statistics launches of D3Q15 / D3Q19, one cell per lane
+
+// Waves per block a step-kernel instantiation is built for.  The FP32
+// statistics launches of D3Q15 and D3Q19 with one cell per lane fit 16 waves
+// in a CU's registers (at most 128 VGPRs) and run two z waves of a whole row
+// per block; every other instantiation stays at 8 (D3Q27 and wider lanes need
+// more registers).
+constexpr int step_max_waves(int store_bytes, int q, int vec, bool stats) {
+  return (stats && store_bytes == 4 && q <= 19 && vec == 1) ? kMaxWavesWide : kMaxWavesPerBlock;
+}
 constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel (2048 / rows for 4 and 8 rows)
 constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
 constexpr int kStgBatch = 8;        // inlet planes generated per STG launch during stepping
