@@ -218,6 +218,40 @@ def test_full_size_front_parity(cfg_index, steps):
     lat.close()
 
 
+def test_full_size_statistics_front_parity():
+    """FP64 statistics of the full 512x128x256 FP32 channel in the bench's launch shape.
+
+    The statistics launch runs whole-row blocks of two z waves with 128-row z
+    chunks (2 FP64 slots), waves in step, so this is the one test whose
+    statistics pass through that shape with many rows per wave.  From rest,
+    after K sampled steps the bins x <= K match an oracle channel of 2K + 2
+    planes with the same inlet (as in the front test above), and every bin
+    beyond K sums a velocity that is exactly zero.
+    """
+    steps = 8
+    cfg = channel_config(1)
+    assert cfg["store"] == "f32" and (cfg["nx"], cfg["ny"], cfg["nz"]) == (512, 128, 256)
+    lat = _lat(cfg)
+    lat.stats_reset()
+    lat.step(steps)
+    st, ns = lat.get_stats()
+    sub = dict(cfg)
+    sub["nx"] = 2 * steps + 2
+    sub["sponge_cells"] = 0
+    ora = OracleChannel.from_config(sub)
+    ora.stats_reset()
+    ora.step(steps)
+    got, ref = st[: steps + 1], ora.stats[: steps + 1]
+    nrm = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    worst = max(np.abs(got[..., q] - ref[..., q]).max() / np.abs(ref[..., q]).max() for q in range(9))
+    print(f"[gpu] channel-512x128x256 statistics after {steps} steps: normwise rel err {nrm:.3e}, "
+          f"worst quantity (max-normalized) {worst:.3e}", flush=True)
+    assert ns == steps
+    assert nrm < 1e-6 and worst < 1e-6
+    assert not st[steps + 1:].any()
+    lat.close()
+
+
 @pytest.mark.parametrize("store,unit", [("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)])
 def test_half_store_against_oracle(store, unit):
     """FP16/BF16 deviation store against the FP64 oracle, with a derived bound.
