@@ -124,9 +124,10 @@ Layout make_layout(const stglbm_lattice_desc* d) {
     // and 4 slots 0.457; one z wave: 4 slots 0.476, 8: 0.482, 16: 0.494;
     // half rows with four z waves 0.477-0.479); with one z wave the two
     // 8-wave blocks sharing a CU ran at different speeds, and the first to
-    // finish left the CU half empty for the last 10-25 % of the launch.  FP16 0.273 ms (two z waves 0.298), BF16 0.297
-    // (8 slots: 0.303); 1024x256x512 FP16: 16 slots within 0.3 % of 8, 4
-    // slots 3 % slower.
+    // finish left the CU half empty for the last 10-25 % of the launch.
+    // FP16 0.273 ms (8 slots 0.274, 4 slots 0.278, two z waves 0.298, half
+    // rows 0.299), BF16 0.282 (8 slots 0.291); 1024x256x512 FP16: 16 slots
+    // within 0.3 % of 8, 4 slots 3 % slower.
     const bool f32 = d->store == STGLBM_F32;
     if (L.short_chunks_when_idle && step_max_waves(store_bytes(d->store), set_size(d), vec, true) == kMaxWavesWide) wz = 2;
     L.wz = wz;

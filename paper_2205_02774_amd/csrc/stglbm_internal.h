@@ -11,6 +11,9 @@ constexpr int kModeFields = 8;      // k, d(3), sigma(3), phi
 constexpr int kScalars = 8;         // L_e k_min k_max alpha k_cut clamps U_b N
 constexpr int kMaxWavesPerBlock = 8; // step kernel: waves along x times waves along z
 constexpr int kMaxWavesWide = 16;    // FP32 statistics launches of D3Q15 / D3Q19, one cell per lane
+constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel (2048 / rows for 4 and 8 rows)
+constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
+constexpr int kStgBatch = 8;        // inlet planes generated per STG launch during stepping
 
 // Waves per block a step-kernel instantiation is built for.  The FP32
 // statistics launches of D3Q15 and D3Q19 with one cell per lane fit 16 waves
@@ -20,9 +23,6 @@ constexpr int kMaxWavesWide = 16;    // FP32 statistics launches of D3Q15 / D3Q1
 constexpr int step_max_waves(int store_bytes, int q, int vec, bool stats) {
   return (stats && store_bytes == 4 && q <= 19 && vec == 1) ? kMaxWavesWide : kMaxWavesPerBlock;
 }
-constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel (2048 / rows for 4 and 8 rows)
-constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
-constexpr int kStgBatch = 8;        // inlet planes generated per STG launch during stepping
 
 // Flag bits written by the kernels into the handle's status word.
 constexpr int kFlagDensity = 1;     // |rho - 1| >= 0.5 or NaN in the step kernel
