@@ -316,6 +316,50 @@ def test_half_store_rounding_is_nearest_even():
         lat.close()
 
 
+def test_half_store_rounding_ties():
+    """Exact ties of the FP32 deviation go to the even 16-bit neighbour.
+
+    The deviations are FP32 numbers placed exactly halfway between two
+    neighbouring BF16 (low 16 bits 0x8000) or FP16 values, with both parities
+    of the kept last bit, so round-half-up or truncation would fail here;
+    f = w + g is exact in FP64, so the import sees these FP32 values exactly.
+    The expected value is torch's round-to-nearest-even conversion on the CPU.
+    """
+    from paper_2205_02774_amd import Lattice
+    from oracle.lattice import W
+    nx, ny, nz = 16, 4, 2
+    rng = np.random.default_rng(11)
+    n = 19 * nz * ny * nx
+    mag = rng.uniform(1e-4, 1e-2, n) * rng.choice([-1.0, 1.0], n)
+    # BF16 ties: keep the top 16 bits of an FP32 value and set the next bit only
+    bits = mag.astype(np.float32).view(np.uint32)
+    g_bf = ((bits & np.uint32(0xFFFF0000)) | np.uint32(0x8000)).view(np.float32)
+    # FP16 ties: the midpoint of an FP16 value and its upper neighbour (exact in FP32)
+    h = mag.astype(np.float16)
+    h_up = np.nextafter(h, np.float16(np.inf) * np.sign(h).astype(np.float16))
+    g_h = ((h.astype(np.float32) + h_up.astype(np.float32)) * np.float32(0.5)).astype(np.float32)
+    assert np.all(g_h.astype(np.float16) != g_h)                      # really between two FP16 values
+    cases = {
+        "bf16": (g_bf, torch.from_numpy(g_bf.copy()).to(torch.bfloat16).to(torch.float64).numpy()),
+        "f16": (g_h, g_h.astype(np.float16).astype(np.float64)),
+    }
+    for store, (g32, want) in cases.items():
+        g = g32.astype(np.float64).reshape(19, nz, ny, nx)
+        f = W[:, None, None, None] + g
+        assert np.array_equal(f - W[:, None, None, None], g)           # the import sees g exactly
+        lat = Lattice(nx, ny, nz, device="cuda:0", store=store, periodic_x=True, nu_lb=1e-2)
+        lat.set_f(f)
+        back = (lat.get_f() - W[:, None, None, None]).reshape(-1)
+        lat.close()
+        if store == "bf16":
+            even = ((want.astype(np.float32).view(np.uint32) >> 16) & 1) == 0
+        else:
+            even = (want.astype(np.float16).view(np.uint16) & 1) == 0
+        print(f"[gpu] {store} ties: {int((back == want).sum())} of {n} to the even neighbour "
+              f"(reference even everywhere: {bool(even.all())})", flush=True)
+        assert even.all() and np.array_equal(back, want)
+
+
 def test_determinism_and_checkpoint_restore():
     cfg = channel_config(0)
     a = _lat(cfg)
