@@ -119,21 +119,21 @@ Layout make_layout(const stglbm_lattice_desc* d) {
     // two z waves per block (whole rows, 16 waves: one block fills a CU's
     // wave slots, so all its waves run in step and finish together), 2 slots,
     // more where the grid would hold fewer than 4096 waves.  Other FP32 sets:
-    // one z wave, 4 slots.  16-bit stores: one z wave, 16 slots and 8192
-    // waves.  Measured on MI355X, 512x128x256: FP32 0.455 ms (two z waves
-    // and 4 slots 0.457; one z wave: 4 slots 0.476, 8: 0.482, 16: 0.494;
+    // one z wave, 4 slots.  16-bit stores: one z wave and as many slots as
+    // make 16384 waves.  Measured on MI355X, 512x128x256: FP32 0.455 ms (two
+    // z waves and 4 slots 0.457; one z wave: 4 slots 0.476, 8: 0.482, 16: 0.494;
     // half rows with four z waves 0.477-0.479); with one z wave the two
     // 8-wave blocks sharing a CU ran at different speeds, and the first to
     // finish left the CU half empty for the last 10-25 % of the launch.
-    // FP16 0.273 ms (8 slots 0.274, 4 slots 0.278, two z waves 0.298, half
-    // rows 0.299), BF16 0.282 (8 slots 0.291); 1024x256x512 FP16: 16 slots
-    // within 0.3 % of 8, 4 slots 3 % slower.
+    // FP16 (16 slots) 0.273 ms (8 slots 0.274, 4 slots 0.278, two z waves
+    // 0.298, half rows 0.299); 1024x256x512 FP16 (4 slots) 2.098 ms (8 slots
+    // 2.103, 16 slots 2.143, 2 slots 2.171): both best at 16384 waves.
     const bool f32 = d->store == STGLBM_F32;
     if (L.short_chunks_when_idle && step_max_waves(store_bytes(d->store), set_size(d), vec, true) == kMaxWavesWide) wz = 2;
     L.wz = wz;
     const int zmax = (d->nz + wz - 1) / wz;
     const int waves = base * wx * wz;
-    const int min_waves = f32 ? 4096 : 8192, min_slots = wz == 2 ? 2 : (f32 ? 4 : 16);
+    const int min_waves = f32 ? 4096 : 16384, min_slots = wz == 2 ? 2 : (f32 ? 4 : 1);
     int slots = (min_waves + waves - 1) / waves;
     if (slots < min_slots) slots = min_slots;
     if (slots > zmax) slots = zmax;

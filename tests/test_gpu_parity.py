@@ -218,23 +218,22 @@ def test_full_size_front_parity(cfg_index, steps):
     lat.close()
 
 
-@pytest.mark.parametrize("cfg_index,qset", [(1, 19), (1, 27), (2, 19)])
-def test_full_size_statistics_front_parity(cfg_index, qset):
-    """FP64 statistics of the full 512x128x256 channel in the bench's launch shapes.
+@pytest.mark.parametrize("cfg_index,qset,steps", [(1, 19, 8), (1, 27, 8), (2, 19, 8), (3, 19, 4)])
+def test_full_size_statistics_front_parity(cfg_index, qset, steps):
+    """FP64 statistics of the full-size channels in the bench's launch shapes.
 
     Each statistics launch shape passes through here with many z rows per
     wave: FP32 D3Q19 (whole-row blocks of two z waves, 128-row chunks, 2 FP64
     slots), FP32 D3Q27 (one z wave, 64-row chunks, 4 slots) and FP16 (one z
-    wave, 16-row chunks, 16 slots).  From rest, after K sampled steps the bins
+    wave; 16-row chunks and 16 slots at 512x128x256, 128-row chunks and 4
+    slots at 1024x256x512).  From rest, after K sampled steps the bins
     x <= K match an oracle channel of 2K + 2 planes with the same inlet (as in
     the front test above), and every bin beyond K sums a velocity that is
     exactly zero.  FP32: the 1e-6 bar.  FP16: each step's rounding of g moves
     u by about unit * |u| (g carries u linearly), over K independent steps
     and doubled for the quadratic sums: 8 sqrt(K) unit, normwise.
     """
-    steps = 8
     cfg = channel_config(cfg_index)
-    assert (cfg["nx"], cfg["ny"], cfg["nz"]) == (512, 128, 256)
     lat = _lat(cfg, velocity_set=qset)
     lat.stats_reset()
     lat.step(steps)
