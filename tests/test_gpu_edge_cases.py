@@ -107,16 +107,21 @@ def test_profile_times_one_launch_in_every():
     lat.close()
 
 
-@pytest.mark.parametrize("store", ["f32", "f16"])
-def test_rows_wider_than_one_block_with_idle_waves(store):
-    """NX = 581: 10 tiles of 64, whole-row blocks of 8 waves, so the second
+@pytest.mark.parametrize("store,shape", [("f32", (581, 4, 6)), ("f16", (581, 4, 6)), ("f32", (1030, 4, 8))])
+def test_rows_wider_than_one_block_with_idle_waves(store, shape):
+    """Rows wider than one block, the last block of a row partly idle.
+
+    NX = 581: 10 tiles of 64, whole-row blocks of 8 waves, so the second
     block of each row has 2 working waves and 6 that only keep step with
-    them (FP32 statistics launches hold a barrier per z row)."""
+    them (statistics launches hold a barrier per z row; FP32 ones run two z
+    waves per block).  NX = 1030: 17 tiles in three blocks per row, the
+    third with one working wave; its 48 FP32 statistics blocks are renumbered
+    so that the three blocks of a row share an XCD."""
     from paper_2205_02774_amd import Lattice
     from oracle.lattice import W
-    nx, ny, nz = 581, 4, 6
+    nx, ny, nz = shape
     nu, cs, force = 2e-2, 0.1, (1e-5, 0.0, 0.0)
-    print(f"[gpu] edge wide rows {store}", flush=True)
+    print(f"[gpu] edge wide rows {store} {shape}", flush=True)
     lat = Lattice(nx, ny, nz, device="cuda:0", store=store, periodic_x=True, nu_lb=nu, cs_smag=cs, force=force)
     ora = OracleChannel(nx, ny, nz, nu_lb=nu, cs_smag=cs, force=force, periodic_x=True)
     rng = np.random.default_rng(11)
@@ -131,7 +136,7 @@ def test_rows_wider_than_one_block_with_idle_waves(store):
     lat.close()
     rel = _rel(f, ora.f)
     nrm = np.linalg.norm(st - ora.stats) / np.linalg.norm(ora.stats)
-    print(f"[gpu] edge wide rows {store}: max rel err f {rel.max():.3e}, stats {nrm:.3e}", flush=True)
+    print(f"[gpu] edge wide rows {store} {shape}: max rel err f {rel.max():.3e}, stats {nrm:.3e}", flush=True)
     assert n == 30
     if store == "f32":
         assert rel.max() < 1e-6 and nrm < 1e-6
