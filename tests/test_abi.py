@@ -100,6 +100,28 @@ def test_derive_units_matches_oracle(lib):
     assert got == pytest.approx((c_x, c_t, nu_lb), rel=1e-15)
 
 
+@pytest.mark.parametrize("shape,store,qset,slots", [
+    ((512, 128, 256), "f32", 19, 2),     # two z waves per block, 2 x 128 x 16 waves = 4096
+    ((512, 128, 256), "f32", 15, 2),
+    ((512, 128, 256), "f32", 27, 4),     # one z wave: 4 slots
+    ((512, 128, 256), "f16", 19, 16),    # 16-bit: slots for 16384 waves, 1024 per slot
+    ((512, 128, 256), "bf16", 19, 16),
+    ((1024, 256, 512), "f16", 19, 4),    # 4096 waves per slot
+    ((64, 32, 32), "f32", 19, 16),       # capped at NZ / 2 for two z waves
+    ((64, 32, 32), "f16", 19, 32),       # capped at NZ
+])
+def test_statistics_slots_of_the_launch_shape(lib, shape, store, qset, slots):
+    """The FP64 statistics slots the layout reserves follow the launch-shape
+    rule: periodic lattices hold the two distribution buffers, the slots and
+    under 1 MiB of small tables, so the slot count is read off the footprint."""
+    from paper_2205_02774_amd import make_desc, footprint
+    nx, ny, nz = shape
+    fp = footprint(make_desc(nx, ny, nz, nu_lb=1e-3, store=store, periodic_x=True, velocity_set=qset))
+    g = 2 * qset * nx * ny * nz * (4 if store == "f32" else 2)
+    bins = 9 * nx * ny * 8
+    assert slots * bins <= fp - g < slots * bins + 2 ** 20
+
+
 def test_velocity_set_and_collision_validation(lib):
     from paper_2205_02774_amd import abi, make_desc, footprint
     base = footprint(make_desc(64, 32, 32, nu_lb=1e-3, periodic_x=True))
