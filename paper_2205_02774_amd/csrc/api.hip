@@ -42,6 +42,7 @@ struct Layout {
   int vec = 1, nxt = 0, wx = 1, wz = 1, nxg = 0, slots = 0, lw = 0, zstep = 1, nblocks = 0;
   bool short_chunks_when_idle = true;   // steps without statistics: their own shape
   int wx_idle = 1, nxg_idle = 1, lw_idle = 1;
+  int remap_env = -1, lockstep = 1;   // tuning overrides read once per handle (-1: no override)
 };
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -104,6 +105,8 @@ Layout make_layout(const stglbm_lattice_desc* d) {
     }
   }
   if (set_size(d) != 19 || d->collision != 0) vec = 1;   // the variants are built for one cell per lane
+  if (const char* env = std::getenv("STGLBM_REMAP")) L.remap_env = std::atoi(env) ? 1 : 0;
+  if (const char* env = std::getenv("STGLBM_LOCKSTEP")) L.lockstep = std::atoi(env) ? 1 : 0;
   L.vec = vec;
   L.nxt = (d->nx + 64 * vec - 1) / (64 * vec);
   const int wx_row = L.nxt < 8 ? L.nxt : 8;   // whole rows of up to 8 tiles
@@ -302,11 +305,10 @@ StepParams step_params(stglbm_t h) {
   // One block per row (nxg = 1): the hardware's turn-by-turn XCD order is
   // kept (a contiguous range per XCD measured 3 % slower on 512x128x256).
   p.remap = (p.nxg > 1 && p.nblocks % (8 * p.nxg) == 0) ? 1 : 0;
-  if (const char* env = std::getenv("STGLBM_REMAP")) p.remap = std::atoi(env) && p.nxg > 1 && p.nblocks % (8 * p.nxg) == 0;
-  // Statistics launches keep their waves in step (512x128x256: FP32 0.505 ->
-  // 0.499 ms, FP16 0.289 -> 0.273 ms).
-  p.lockstep = 1;
-  if (const char* env = std::getenv("STGLBM_LOCKSTEP")) p.lockstep = std::atoi(env) ? 1 : 0;
+  if (h->L.remap_env >= 0) p.remap = h->L.remap_env && p.nxg > 1 && p.nblocks % (8 * p.nxg) == 0;
+  // Statistics launches keep their waves in step (512x128x256: FP32 with two
+  // z waves 0.514 -> 0.458 ms, FP16 0.289 -> 0.273 ms).
+  p.lockstep = h->L.lockstep;
   p.periodic_x = d.periodic_x;
   p.has_force = (d.force[0] != 0.0 || d.force[1] != 0.0 || d.force[2] != 0.0) ? 1 : 0;
   const double tau0 = 0.5 + 3.0 * d.nu_lb;
