@@ -143,3 +143,31 @@ def test_rows_wider_than_one_block_with_idle_waves(store, shape):
     else:
         # 16-bit store: every step rounds g to 2^-11 relative; |g/f| <= 1e-2 here
         assert rel.max() < 4 * np.sqrt(30) * 2.0 ** -11 * 2e-2 and nrm < 1e-3
+
+
+def test_statistics_without_per_row_barrier(monkeypatch):
+    """The tuning override STGLBM_LOCKSTEP=0 drops the per-row barrier of the
+    statistics launches (the two z waves of an FP32 block then run free and
+    may leave the z loop at different trips); results stay those of the oracle."""
+    from paper_2205_02774_amd import Lattice
+    from oracle.lattice import W
+    monkeypatch.setenv("STGLBM_LOCKSTEP", "0")
+    nx, ny, nz = 581, 4, 7
+    nu, cs, force = 2e-2, 0.1, (1e-5, 0.0, 0.0)
+    print("[gpu] edge statistics without the per-row barrier", flush=True)
+    lat = Lattice(nx, ny, nz, device="cuda:0", periodic_x=True, nu_lb=nu, cs_smag=cs, force=force)
+    ora = OracleChannel(nx, ny, nz, nu_lb=nu, cs_smag=cs, force=force, periodic_x=True)
+    rng = np.random.default_rng(12)
+    lat.set_f(W[:, None, None, None] * (1.0 + 1e-2 * rng.uniform(-1, 1, (19, nz, ny, nx))))
+    ora.set_f(lat.get_f())
+    lat.stats_reset()
+    ora.stats_reset()
+    lat.step(20)
+    ora.step(20)
+    st, n = lat.get_stats()
+    f = lat.get_f()
+    lat.close()
+    rel = _rel(f, ora.f)
+    nrm = np.linalg.norm(st - ora.stats) / np.linalg.norm(ora.stats)
+    print(f"[gpu] edge no barrier: max rel err f {rel.max():.3e}, stats {nrm:.3e}", flush=True)
+    assert n == 20 and rel.max() < 1e-6 and nrm < 1e-6
