@@ -150,7 +150,7 @@ int stglbm_set_rans_inlet(stglbm_t h, const stglbm_rans_inlet* in);
 int stglbm_stg_generate(stglbm_t h, int64_t t_step, float* d_u_plane);
 
 /* Advance n_steps time steps (Algorithm 1, steps 5-12): for each step the STG
- * plane at t+1 (one launch makes the planes of 8 consecutive steps, kept until
+ * plane at t+1 (one launch makes the planes of 16 consecutive steps, kept until
  * used, also by later calls), then one fused pass: pull streaming with
  * bounce-back walls and spanwise wrap, regularized inlet rebuild (eqs. f_i ..
  * bc_eq) behind the guard |u_x| < 0.3 c_s, regularized pressure outlet,

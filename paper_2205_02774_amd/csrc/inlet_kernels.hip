@@ -16,7 +16,7 @@
 // FP64 per (row, mode, step), and a spanwise part k^n d^n_z z held as an FP32
 // phasor.  Their product gives cos of the full phase without a large-argument
 // FP32 cosine.  A block owns 1 to 8 rows and 64 spanwise nodes of one plane
-// (one launch makes the planes of up to 8 steps); its 8 waves split the
+// (one launch makes the planes of up to 16 steps); its 8 waves split the
 // modes, the row phasors and sigma^n are staged in LDS per chunk of modes,
 // and the waves' partial sums meet in LDS.
 #include <cstdlib>

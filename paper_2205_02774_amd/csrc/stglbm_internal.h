@@ -13,7 +13,7 @@ constexpr int kMaxWavesPerBlock = 8; // step kernel: waves along x times waves a
 constexpr int kMaxWavesWide = 16;    // FP32 statistics launches of D3Q15 / D3Q19, one cell per lane
 constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel (2048 / rows for 4 and 8 rows)
 constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
-constexpr int kStgBatch = 8;        // inlet planes generated per STG launch during stepping
+constexpr int kStgBatch = 16;       // inlet planes generated per STG launch during stepping
 
 // Waves per block a step-kernel instantiation is built for.  The FP32
 // statistics launches of D3Q15 and D3Q19 with one cell per lane fit 16 waves

@@ -69,7 +69,7 @@ def test_descriptor_validation_and_footprint(lib):
     fp = footprint(d)
     g32 = 2 * 19 * 512 * 128 * 256 * 4
     bins = 9 * 512 * 128 * 8                          # one FP64 statistics slot
-    ring = 8 * 128 * 256 * 3 * 4                      # inlet planes of 8 steps, FP32
+    ring = 16 * 128 * 256 * 3 * 4                     # inlet planes of 16 steps, FP32
     assert fp >= g32
     # two distribution buffers + FP64 statistics slots (at most 16) + the plane ring + the small inlet tables
     assert fp - g32 <= 16 * bins + ring + 4 * 2 ** 20

@@ -90,9 +90,9 @@ def test_profile_times_one_launch_in_every():
     cfg = small_channel(24, 16, 8, n_modes=10, seed=3)
     lat = channel_from_config(cfg, device="cuda:0")
     lat.profile(True, every=4)
-    lat.step(10)
+    lat.step(20)            # steps 0, 4, ..., 16 timed; planes made 16 at a time: 2 STG launches
     pr = lat.profile_read()
-    assert pr["step_launches"] == 3 and pr["stg_launches"] == 2 and pr["stg_planes"] == 16
+    assert pr["step_launches"] == 5 and pr["stg_launches"] == 2 and pr["stg_planes"] == 32
     assert pr["step_ms"] > 0.0 and pr["stg_ms"] > 0.0
     lat.profile(True)
     lat.step(5)

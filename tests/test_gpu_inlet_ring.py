@@ -1,4 +1,4 @@
-"""Inlet planes made ahead: one STG launch writes the planes of 8 consecutive
+"""Inlet planes made ahead: one STG launch writes the planes of 16 consecutive
 steps, which stglbm_step keeps until used, also across calls.  The results
 do not depend on how the steps are split into calls or streams, and a new
 inlet takes effect at the next step although planes of the old one were
