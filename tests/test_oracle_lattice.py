@@ -166,6 +166,81 @@ def test_poiseuille_second_order():
     assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.05)
 
 
+def _smagorinsky_poiseuille(eta, H, nu0, cs, F):
+    """Steady laminar channel with the Smagorinsky viscosity, in closed form.
+
+    The momentum balance of a forced channel (walls at eta = 0 and H) fixes the
+    shear stress, nu_eff U' = F (H/2 - eta).  In simple shear |S| = sqrt(2 S:S)
+    = |U'|, so with nu_eff = nu0 + C |S| (filter width = lattice spacing,
+    C = Cs^2) the balance (nu0 + C U') U' = F (H/2 - eta) is a quadratic in U'
+    for eta < H/2.  With g = F (H/2 - eta),
+        U' = (sqrt(nu0^2 + 4 C g) - nu0) / (2 C),
+    and since dg = -F d(eta), U(eta) = (G(F H/2) - G(g(eta))) / F with
+        G(g) = ((nu0^2 + 4 C g)^(3/2) / (6 C) - nu0 g) / (2 C).
+    The profile is symmetric about H/2.
+    """
+    c = cs * cs
+
+    def G(g):
+        return ((nu0 ** 2 + 4.0 * c * g) ** 1.5 / (6.0 * c) - nu0 * g) / (2.0 * c)
+
+    e = np.minimum(eta, H - eta)
+    return (G(F * H / 2.0) - G(F * (H / 2.0 - e))) / F
+
+
+def test_smagorinsky_poiseuille_second_order():
+    """The Smagorinsky chain (Pi_neq -> Q^1/2 -> tau_eff, eqs. tensor, strain, tau_eff)
+    against the closed-form Smagorinsky-Poiseuille profile, converging at second order.
+
+    The resolutions are related by diffusive scaling with a fixed filter width in
+    physical units: tau0 fixed, F ~ NY^-3 and Cs ~ NY, so every NY solves the same
+    problem (Smagorinsky viscosity about a quarter of nu0 at the walls; the profile
+    differs from the Cs = 0 parabola by 15 % of its maximum).  The run starts from
+    f_eq of the closed form and steps until the transient is well below the
+    discretisation error.  A wrong factor anywhere in the chain (the sqrt 2, C versus
+    Cs, the Frobenius norm, rho) gives another steady profile, and the error would
+    then stop falling with NY.
+    """
+    nu0 = 0.2
+    errs = []
+    for ny, cs in ((16, 2.1), (32, 4.2), (64, 8.4)):
+        F = 3.125e-4 * (16.0 / ny) ** 3
+        ch = OracleChannel(1, ny, 1, nu_lb=nu0, cs_smag=cs, force=(F, 0.0, 0.0), periodic_x=True)
+        eta = np.arange(ny) + 0.5
+        exact = _smagorinsky_poiseuille(eta, ny, nu0, cs, F)
+        u0 = np.zeros((3, 1, ny, 1))
+        u0[0, 0, :, 0] = exact
+        ch.set_f(L.equilibrium(np.ones((1, ny, 1)), u0))
+        ch.step(int(0.6 * ny * ny / nu0))
+        errs.append(np.abs(ch.last_u[0, 0, :, 0] - exact).max() / exact.max())
+        parabola = F / (2.0 * nu0) * eta * (ny - eta)
+        assert np.abs(parabola - exact).max() / exact.max() > 0.15       # the model term matters
+        np.testing.assert_allclose(ch.last_u[1:], 0.0, atol=1e-14)
+    assert errs[2] < 4e-4
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.03)
+    assert errs[1] / errs[2] == pytest.approx(4.0, rel=0.03)
+
+
+def test_q_half_of_simple_shear():
+    """Q^1/2 = sqrt(Pi:Pi): sqrt(2) |s| for a simple shear Pi_xy = Pi_yx = s, and the
+    norm of a rotated tensor is unchanged (the Frobenius norm is rotation invariant)."""
+    s = np.array([3e-4, -2e-3])
+    pi = np.zeros((3, 3, 2))
+    pi[0, 1] = pi[1, 0] = s
+    np.testing.assert_allclose(L.q_half(pi), math.sqrt(2.0) * np.abs(s), rtol=1e-15)
+    # the non-equilibrium of f_eq + Hermite part carries Pi exactly, so Q^1/2 follows
+    f = L.equilibrium(np.ones(2), np.zeros((3, 2))) + L.hermite_part(pi)
+    pi_back = L.second_moment(f - L.equilibrium(L.density(f), L.velocity(f, L.density(f), (0, 0, 0))))
+    np.testing.assert_allclose(L.q_half(pi_back), math.sqrt(2.0) * np.abs(s), rtol=1e-12)
+    rng = np.random.default_rng(5)
+    A = rng.normal(size=(3, 3))
+    A = A + A.T
+    Rm, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    B = Rm @ A @ Rm.T
+    assert L.q_half(A[:, :, None])[0] == pytest.approx(np.sqrt((np.linalg.eigvalsh(A) ** 2).sum()), rel=1e-13)
+    assert L.q_half(B[:, :, None])[0] == pytest.approx(L.q_half(A[:, :, None])[0], rel=1e-13)
+
+
 def test_stream_matches_push_bruteforce():
     """Pull streaming with halfway bounce-back equals an explicit push loop."""
     nz, ny, nx = 3, 4, 5

@@ -100,6 +100,26 @@ def test_length_scales_and_cutoff():
     np.testing.assert_allclose(stg.cutoff_length(0.1, 0.1, 0.1, np.array([0.0, 1.0])), [0.2, 0.2])
 
 
+def test_length_scales_log_layer():
+    """The RANS length scale against the log law (l_t of the STG section).
+
+    In the log layer production balances dissipation, eps = u_tau^3/(kappa y), and
+    the eddy viscosity is the mixing-length one, nu_t = kappa y u_tau; the k-omega
+    model's log-layer solution is k = u_tau^2/sqrt(C_mu), omega = k/nu_t (Wilcox).
+    The integral length k^(3/2)/eps of that flow is kappa y C_mu^(-3/4), and l_t
+    must equal it; l_e is then 2 d_w, since C_l l_t = 7.5 y exceeds 2 y there.
+    """
+    kappa, C_mu, u_tau = 0.41, 0.09, 0.7
+    y = np.array([0.02, 0.05, 0.1, 0.2])
+    k = np.full_like(y, u_tau ** 2 / math.sqrt(C_mu))
+    omega = k / (kappa * y * u_tau)
+    l_t, l_e = stg.length_scales(k, omega, y, 3.0, C_mu)
+    eps = u_tau ** 3 / (kappa * y)
+    np.testing.assert_allclose(l_t, k ** 1.5 / eps, rtol=1e-14)
+    np.testing.assert_allclose(l_t, kappa * y * C_mu ** -0.75, rtol=1e-14)
+    np.testing.assert_allclose(l_e, 2.0 * y, rtol=1e-15)
+
+
 def test_mode_count_and_wavenumbers():
     assert stg.mode_count(100.0, 1.0, 0.01) == 464        # ceil(462.8 + 1)
     kn, a = stg.wavenumbers(2.0, 300.0, 600, 0.0)
@@ -221,3 +241,97 @@ def test_inlet_plane_guard_and_units(cfg_index):
     expect = gen.U_int[:, 0].mean() * gen.c_t / gen.c_x
     assert mean == pytest.approx(expect, rel=0.05)
     assert expect == pytest.approx(cfg["u_b_lb"], rel=0.02 if cfg_index == 0 else 0.05)
+
+
+def _seed_fields(S, positions, seed0):
+    """v' of the fixed-geometry generator for S seeds, evaluated by `positions(seed index, draw)`."""
+    kn, sq, q = _fixed_geometry()
+    out = []
+    for s in range(S):
+        d, sigma, ph = stg.draw_modes(seed0 + s, kn.size)
+        out.append(positions(kn, sq, d, sigma, ph))
+    return kn, q, np.array(out)
+
+
+def _within(est, se, expect, k=5.0):
+    return np.all(np.abs(est - expect) <= k * se)
+
+
+def test_stg_spanwise_two_point_correlation():
+    """Ensemble spanwise correlation of v' (eqs. aux_vec, psu) against its closed form.
+
+    With phases uniform and independent, E[cos(A + phi) cos(B + phi)] = cos(A - B)/2
+    and the modes decorrelate, so for a spanwise separation r
+        tr E[v'(z) v'(z + r)] = 3 sum_n q^n E[cos(k^n d_z r)] = 3 sum_n q^n sin(k^n r)/(k^n r),
+    since d_z is uniform on [-1, 1] for directions uniform on the sphere.  For the
+    spanwise component, E[sigma_z^2 | d] = (1 - d_z^2)/2 (sigma uniform on the circle
+    normal to d), giving E[w'(z) w'(z + r)] = 3 sum_n q^n (sin b - b cos b)/b^3, b = k^n r.
+    A wavenumber scaled by 2 pi (or its inverse) in the spatial part of the phase, or
+    sigma not normal to d, moves these curves by many standard errors (checked below).
+    """
+    r = np.array([0.0, 0.05, 0.1, 0.2, 0.35, 0.6, 1.0])
+    z0 = np.linspace(0.0, 70.0, 8)          # base points far apart (several correlation lengths)
+    z = (z0[:, None] + r[None, :]).ravel()
+    y = np.array([0.45])
+    L_e, U_b, t = 1.9, 15.5, 0.21
+
+    def field(kn, sq, d, sigma, ph):
+        v = stg.auxiliary_field(t, 0.0, y, z, kn, d, sigma, ph, sq, L_e, U_b)[0].reshape(len(z0), len(r), 3)
+        tr = np.einsum("pa,pra->pr", v[:, 0, :], v).mean(0)
+        ww = (v[:, 0, 2][:, None] * v[:, :, 2]).mean(0)
+        return np.concatenate([tr, ww])
+
+    S = 1500
+    kn, q, X = _seed_fields(S, field, 50_000)
+    est, se = X.mean(0), X.std(0, ddof=1) / math.sqrt(S)
+    b = np.outer(r, kn)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        sinc = np.where(b > 0, np.sin(b) / b, 1.0)
+        g = np.where(b > 0, (np.sin(b) - b * np.cos(b)) / b ** 3, 1.0 / 3.0)
+    tr_expect = 3.0 * sinc @ q
+    ww_expect = 3.0 * g @ q
+    n = len(r)
+    assert tr_expect[0] == pytest.approx(3.0) and ww_expect[0] == pytest.approx(1.0)
+    assert _within(est[:n], se[:n], tr_expect), (est[:n], tr_expect, se[:n])
+    assert _within(est[n:], se[n:], ww_expect), (est[n:], ww_expect, se[n:])
+    # the test separates plausible mistakes in the wavenumber scaling
+    for wrong in (2.0 * np.pi, 1.0 / (2.0 * np.pi)):
+        bw = b * wrong
+        with np.errstate(invalid="ignore", divide="ignore"):
+            alt = 3.0 * np.where(bw > 0, np.sin(bw) / bw, 1.0) @ q
+        assert not _within(est[:n], se[:n], alt)
+    # ... and sigma taken along d instead of normal to it: E[w'w'] -> 3 sum q E[d_z^2 cos]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        alt_ww = 3.0 * np.where(b > 0, sinc - 2.0 * g, 1.0 / 3.0) @ q
+    assert not _within(est[n:], se[n:], alt_ww)
+
+
+def test_stg_temporal_two_point_correlation():
+    """Ensemble correlation of v' at one point over a time lag s (eq. psu).
+
+    The pseudo-position scales the streamwise phase so that every mode advances by
+    2 pi d_x U_b s / max(l_e) over a lag s, whatever its wavenumber; with d_x uniform
+    on [-1, 1] and sum_n q^n = 1 this gives tr E[v'(t) v'(t + s)] = 3 sin(a)/a with
+    a = 2 pi U_b s / max(l_e).  A pseudo-position without the 2 pi/(k^n max l_e)
+    factor would give 3 sum_n q^n sin(k^n U_b s)/(k^n U_b s) instead (checked below).
+    """
+    L_e, U_b = 1.9, 15.5
+    a = np.array([0.0, 0.4, 1.0, 2.0, 3.2, 4.5, 6.0])
+    s_lag = a * L_e / (2.0 * np.pi * U_b)
+    t0 = 3.7
+    y, z = np.array([0.8]), np.linspace(0.35, 70.35, 6)     # base points far apart in z
+
+    def field(kn, sq, d, sigma, ph):
+        v = [stg.auxiliary_field(t0 + s, 0.0, y, z, kn, d, sigma, ph, sq, L_e, U_b)[0] for s in s_lag]
+        return np.array([np.einsum("pa,pa->p", v[0], vs).mean() for vs in v])
+
+    S = 1200
+    kn, q, X = _seed_fields(S, field, 90_000)
+    est, se = X.mean(0), X.std(0, ddof=1) / math.sqrt(S)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        expect = 3.0 * np.where(a > 0, np.sin(a) / a, 1.0)
+    assert _within(est, se, expect), (est, expect, se)
+    bw = np.outer(s_lag * U_b, kn)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        alt = 3.0 * np.where(bw > 0, np.sin(bw) / bw, 1.0) @ q
+    assert not _within(est, se, alt)
