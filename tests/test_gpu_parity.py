@@ -65,7 +65,7 @@ def test_inlet_precompute_parity(cfg_index):
     lat.close()
 
 
-@pytest.mark.parametrize("cfg_index", [0, 1])
+@pytest.mark.parametrize("cfg_index", [0, 1, 3])
 def test_stg_plane_parity(cfg_index):
     cfg = channel_config(cfg_index)
     lat = _lat(cfg)
@@ -156,6 +156,66 @@ def test_ragged_inlet_channel_parity(shape):
     print(f"[gpu] ragged {shape}: max rel err {rel.max():.3e}", flush=True)
     assert rel.max() < FP32_F_TOL
     lat.close()
+
+
+@pytest.mark.parametrize("store,shape", [("f32", (581, 8, 6)), ("f16", (581, 8, 6)),
+                                         ("f32", (1030, 8, 8)), ("f16", (1030, 8, 8))])
+def test_wide_inlet_outlet_channel_parity(store, shape):
+    """Inlet/outlet channels whose rows span several blocks, sponge across a block edge.
+
+    NX = 581: two blocks per row, the outlet lane in the second block's second
+    tile (6 of its 8 waves idle); NX = 1030: three blocks per row, the outlet
+    lane in the third block's only working wave, the row's blocks renumbered
+    onto one XCD.  The 80-cell sponge starts in one block and ends in the next.
+    The run starts from f_eq of a mean flow with smooth streamwise, wall-normal
+    and spanwise variation plus a seeded non-equilibrium part, so the outlet
+    rebuild and the sponge act from the first step, and samples statistics.
+    The map is checked step by step: the GPU runs freely and the oracle
+    restarts from the GPU state before each step (as in the smallest-channel
+    test; these 8-row channels at tau0 - 1/2 = 2e-4 amplify rounding).  FP32:
+    1e-6 of max(|f_i|, w_i).  FP16 store: one rounding of g per step, at most
+    2^-11 |g_i| or, below 2^-14, half the subnormal spacing 2^-25, plus the
+    FP32 bar.  Statistics: accumulated over the
+    same steps on both sides, 1e-6 normwise (FP32) and 4 unit (FP16).
+    """
+    from paper_2205_02774_amd import channel_from_config
+    from oracle import lattice as OL
+    nx, ny, nz = shape
+    cfg = small_channel(nx, ny, nz, n_modes=17, seed=21, store=store)
+    cfg["sponge_cells"] = 80
+    lat = _lat(cfg, store=store)
+    ora = OracleChannel.from_config(cfg)
+    rng = np.random.default_rng(22)
+    x = np.arange(nx)[None, None, :]
+    yy = (np.arange(ny)[None, :, None] + 0.5) / ny
+    zz = np.arange(nz)[:, None, None] / nz
+    u0 = np.zeros((3, nz, ny, nx))
+    u0[0] = 0.04 * 4 * yy * (1 - yy) * (1 + 0.1 * np.sin(2 * np.pi * x / 97.0)) + 0.002 * np.cos(2 * np.pi * zz)
+    u0[1] = 0.002 * np.sin(2 * np.pi * x / 61.0) * np.sin(np.pi * yy)
+    u0[2] = 0.003 * np.cos(2 * np.pi * (x / 43.0 + zz))
+    W4 = OL.W[:, None, None, None]
+    f0 = OL.equilibrium(np.ones((nz, ny, nx)), u0) + 2e-4 * W4 * rng.uniform(-1, 1, (19, nz, ny, nx))
+    lat.set_f(f0)
+    ora.set_f(lat.get_f())
+    lat.stats_reset()
+    ora.stats_reset()
+    # FP16: half an ulp, 2^-11 |g|, or half the subnormal spacing 2^-24 for |g| < 2^-14
+    unit, sub = (2.0 ** -11, 2.0 ** -25) if store == "f16" else (0.0, 0.0)
+    worst = 0.0
+    for _ in range(24):
+        lat.step(1)
+        ora.step(1)
+        f = lat.get_f()
+        bar = unit * np.abs(ora.f - W4) + sub + FP32_F_TOL * np.maximum(np.abs(ora.f), W4)
+        worst = max(worst, float((np.abs(f - ora.f) / bar).max()))
+        ora.set_f(f)
+    st, ns = lat.get_stats()
+    lat.close()
+    nrm = np.linalg.norm(st - ora.stats) / np.linalg.norm(ora.stats)
+    print(f"[gpu] wide channel {store} {shape}: worst one-step err / bar {worst:.3e}, stats {nrm:.3e}", flush=True)
+    assert ns == 24 and ora.t == 24
+    assert worst < 1.0
+    assert nrm < (1e-6 if store == "f32" else 4.0 * unit)
 
 
 @pytest.mark.parametrize("store", ["f32", "f16"])
