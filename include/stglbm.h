@@ -159,6 +159,23 @@ int stglbm_stg_generate(stglbm_t h, int64_t t_step, float* d_u_plane);
  * sampling, FP64 statistics.  Asynchronous on the stream. */
 int stglbm_step(stglbm_t h, int32_t n_steps);
 
+/* stglbm_step for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and results, bit for bit, but the inlet planes computed ahead of the
+ * steps are staged in a static device array of the library (16 MiB, one copy
+ * per GPU, held until the process ends) instead of the handle's plane ring,
+ * and no profiling events are recorded for these steps.  It calls no
+ * allocating routine.  The planes of up to 16 steps are made per STG launch
+ * (fewer if they would not fit) and used within the same call; nothing is
+ * carried between calls, and the handle's own ring is left as it was.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (two handles on two streams at once) race and must be serialized by
+ * the caller.  Errors: E_INVAL if one inlet plane (NY*NZ*3 floats) exceeds
+ * the 16 MiB array, or n_steps < 0; E_STATE before set_rans_inlet on an
+ * inlet channel; E_HIP if the array's device address cannot be obtained.
+ * Periodic-x lattices need no planes and step exactly as stglbm_step. */
+int stglbm_step_noalloc(stglbm_t h, int32_t n_steps);
+
 /* Zero the statistics and start sampling every subsequent step. */
 int stglbm_stats_reset(stglbm_t h);
 /* Stop sampling (statistics are kept). */

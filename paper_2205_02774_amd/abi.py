@@ -63,6 +63,7 @@ _SIGS = {
     "stglbm_set_rans_inlet": (c_int32, [c_void_p, ctypes.POINTER(RansInlet)]),
     "stglbm_stg_generate": (c_int32, [c_void_p, c_int64, c_void_p]),
     "stglbm_step": (c_int32, [c_void_p, c_int32]),
+    "stglbm_step_noalloc": (c_int32, [c_void_p, c_int32]),
     "stglbm_stats_reset": (c_int32, [c_void_p]),
     "stglbm_stats_stop": (c_int32, [c_void_p]),
     "stglbm_get_stats": (c_int32, [c_void_p, P_double, c_uint64, ctypes.POINTER(c_int64)]),

@@ -14,10 +14,17 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace stglbm;
+
+// Static device scratch of stglbm_step_noalloc: the inlet planes of the steps
+// it is about to take.  Every GPU the library runs on holds one copy of it
+// until the process ends; every call on a GPU shares that GPU's copy.
+static constexpr uint64_t kScratchBytes = 16ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -27,6 +34,11 @@ constexpr uint32_t kCkptMagic = 0x5354474cu;   // "STGL"
 constexpr uint32_t kCkptVersion = 3;   // 2: store order [NZ][Q][NY][NX]; 3: velocity set and operator
 
 thread_local std::string g_lib_error;
+
+// Device address of `scratch` per device (looked up once per device).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
 
 // roctx range over a host entry point (shown by rocprofv3 --marker-trace).
 struct TraceRange {
@@ -206,6 +218,7 @@ struct stglbm_ctx {
   stglbm_lattice_desc d{};
   Layout L;
   hipStream_t stream = nullptr;
+  int device = -1;                 // device holding the workspace
   char* ws = nullptr;
   int cur = 0;
   int64_t t = 0;
@@ -331,7 +344,7 @@ StepParams step_params(stglbm_t h) {
 
 // STG planes of the n consecutive steps t_first .. t_first + n - 1, written
 // one after the other to out (n <= kStgBatch), in one launch.
-int launch_planes(stglbm_t h, int64_t t_first, int n, float* out) {
+int launch_planes(stglbm_t h, int64_t t_first, int n, float* out, bool timed_ok = true) {
   StgParams s{};
   s.modes = h->at<double>(h->L.modes);
   s.sqrtq = h->at<double>(h->L.sqrtq);
@@ -347,13 +360,14 @@ int launch_planes(stglbm_t h, int64_t t_first, int n, float* out) {
   for (int b = 0; b < n; ++b)
     s.tphase[b] = kTwoPi * (0.0 - h->U_b * (static_cast<double>(t_first + b) * h->c_t)) / h->L_e;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (h->prof) {
+  const bool timed = timed_ok && h->prof;
+  if (timed) {
     e0 = pooled_event(h->ev_stg, 2 * h->n_stg);
     e1 = pooled_event(h->ev_stg, 2 * h->n_stg + 1);
     if (e0 && e1) HIP_CHECK(h, hipEventRecord(e0, h->stream), "hipEventRecord");
   }
   HIP_CHECK(h, launch_stg(s, h->stream), "STG plane kernel launch");
-  if (h->prof && e0 && e1) {
+  if (timed && e0 && e1) {
     HIP_CHECK(h, hipEventRecord(e1, h->stream), "hipEventRecord");
     ++h->n_stg;
     h->n_planes += static_cast<size_t>(n);
@@ -371,6 +385,66 @@ int ring_plane(stglbm_t h, int64_t t, const float** plane) {
     h->ring_n = kStgBatch;
   }
   *plane = h->at<float>(h->L.ubc) + static_cast<uint64_t>(t - h->ring_t0) * h->plane_floats();
+  return STGLBM_OK;
+}
+
+// One time step: the fused stream-collide launch reading the inlet plane
+// `plane` (null for periodic x), the buffer swap and the probes.  With
+// `timed`, the profiler's events may bracket the launch (they are created on
+// first use, so the allocation-free entry point passes false).
+int step_once(stglbm_t h, const float* plane, bool timed_ok) {
+  StepParams p = step_params(h);
+  p.ubc = plane;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool timed = timed_ok && h->prof && (h->prof_count++ % h->prof_every == 0);
+  if (timed) {
+    e0 = pooled_event(h->ev_step, 2 * h->n_step);
+    e1 = pooled_event(h->ev_step, 2 * h->n_step + 1);
+    if (e0 && e1) HIP_CHECK(h, hipEventRecord(e0, h->stream), "hipEventRecord");
+  }
+  HIP_CHECK(h, launch_step(p, h->d.store, h->sampling, h->stream), "step kernel launch");
+  if (timed && e0 && e1) {
+    HIP_CHECK(h, hipEventRecord(e1, h->stream), "hipEventRecord");
+    ++h->n_step;
+  }
+  h->cur = 1 - h->cur;
+  ++h->t;
+  if (h->sampling) ++h->n_samples;
+  if (h->n_probes > 0 && h->probe_rows < h->probe_capacity) {
+    ProbeParams q{};
+    q.g = h->gbuf(h->cur);
+    q.plane2d = static_cast<long long>(h->d.nx) * h->d.ny;
+    q.q = h->q();
+    q.nx = h->d.nx;
+    q.n = h->n_probes;
+    q.fx = h->d.force[0];
+    q.fy = h->d.force[1];
+    q.fz = h->d.force[2];
+    std::memcpy(q.xyz, h->probe_xyz, sizeof(q.xyz));
+    q.out = h->probe_out + 3 * h->n_probes * h->probe_rows;
+    HIP_CHECK(h, launch_probes(q, h->d.store, h->stream), "probe kernel launch");
+    ++h->probe_rows;
+  }
+  return STGLBM_OK;
+}
+
+// Device address of `scratch` on the handle's device.  The array's name is a
+// host-side stand-in; its device address is looked up once per device, with
+// that device current, and kept.
+int device_scratch(stglbm_t h, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (h->device < 0 || h->device >= kMaxDevices) return fail(h, STGLBM_E_HIP, "step_noalloc: unknown device of the workspace");
+  if (!g_scratch_ptr[h->device]) {
+    int prev = 0;
+    HIP_CHECK(h, hipGetDevice(&prev), "hipGetDevice");
+    if (prev != h->device) HIP_CHECK(h, hipSetDevice(h->device), "hipSetDevice");
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (prev != h->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !ptr) return hip_fail(h, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[h->device] = ptr;
+  }
+  *out = g_scratch_ptr[h->device];
   return STGLBM_OK;
 }
 
@@ -425,6 +499,11 @@ int stglbm_init_lattice(const stglbm_lattice_desc* desc, void* d_workspace, uint
   h->L = L;
   h->stream = static_cast<hipStream_t>(hip_stream);
   h->ws = static_cast<char*>(d_workspace);
+  {
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, d_workspace) == hipSuccess && attr.device >= 0) h->device = attr.device;
+    else if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;
+  }
   // rest state g = 0, statistics 0, flags 0 (fill kernels: safe under graph capture)
   hipError_t e = launch_fill_zero(h->gbuf(0), align_up(h->gbytes()), h->stream);
   if (e == hipSuccess) e = launch_fill_zero(h->at<char>(L.stats), L.sponge - L.stats, h->stream);
@@ -518,40 +597,43 @@ int stglbm_step(stglbm_t h, int32_t n_steps) {
   if (n_steps < 0) return fail(h, STGLBM_E_INVAL, "n_steps < 0");
   if (!h->d.periodic_x && !h->inlet_ready) return fail(h, STGLBM_E_STATE, "set_rans_inlet must precede step");
   for (int32_t s = 0; s < n_steps; ++s) {
-    StepParams p = step_params(h);
+    const float* plane = nullptr;
     if (!h->d.periodic_x) {
-      if (int rc = ring_plane(h, h->t + 1, &p.ubc)) return rc;
+      if (int rc = ring_plane(h, h->t + 1, &plane)) return rc;
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    const bool timed = h->prof && (h->prof_count++ % h->prof_every == 0);
-    if (timed) {
-      e0 = pooled_event(h->ev_step, 2 * h->n_step);
-      e1 = pooled_event(h->ev_step, 2 * h->n_step + 1);
-      if (e0 && e1) HIP_CHECK(h, hipEventRecord(e0, h->stream), "hipEventRecord");
+    if (int rc = step_once(h, plane, true)) return rc;
+  }
+  return STGLBM_OK;
+}
+
+int stglbm_step_noalloc(stglbm_t h, int32_t n_steps) {
+  TraceRange trace("stglbm_step_noalloc");
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  if (n_steps < 0) return fail(h, STGLBM_E_INVAL, "n_steps < 0");
+  uint64_t plane_bytes = 0;
+  if (!h->d.periodic_x) {
+    plane_bytes = h->plane_floats() * sizeof(float);
+    if (plane_bytes > kScratchBytes)
+      return fail(h, STGLBM_E_INVAL, "step_noalloc: one inlet plane (NY*NZ*3 floats) exceeds the library's " +
+                                         std::to_string(kScratchBytes >> 20) + " MiB static scratch");
+    if (!h->inlet_ready) return fail(h, STGLBM_E_STATE, "set_rans_inlet must precede step");
+  }
+  float* planes = nullptr;
+  if (int rc = device_scratch(h, reinterpret_cast<void**>(&planes))) return rc;
+  // Planes of up to kStgBatch consecutive steps, made one batch at a time into
+  // the scratch and used before the next batch overwrites them.
+  const int64_t fit = plane_bytes ? static_cast<int64_t>(kScratchBytes / plane_bytes) : kStgBatch;
+  const int batch = static_cast<int>(std::min<int64_t>(kStgBatch, fit));
+  for (int32_t s = 0; s < n_steps; ++s) {
+    const float* plane = nullptr;
+    if (!h->d.periodic_x) {
+      const int k = s % batch;
+      if (k == 0) {
+        if (int rc = launch_planes(h, h->t + 1, std::min(batch, n_steps - s), planes, false)) return rc;
+      }
+      plane = planes + static_cast<uint64_t>(k) * h->plane_floats();
     }
-    HIP_CHECK(h, launch_step(p, h->d.store, h->sampling, h->stream), "step kernel launch");
-    if (timed && e0 && e1) {
-      HIP_CHECK(h, hipEventRecord(e1, h->stream), "hipEventRecord");
-      ++h->n_step;
-    }
-    h->cur = 1 - h->cur;
-    ++h->t;
-    if (h->sampling) ++h->n_samples;
-    if (h->n_probes > 0 && h->probe_rows < h->probe_capacity) {
-      ProbeParams q{};
-      q.g = h->gbuf(h->cur);
-      q.plane2d = static_cast<long long>(h->d.nx) * h->d.ny;
-      q.q = h->q();
-      q.nx = h->d.nx;
-      q.n = h->n_probes;
-      q.fx = h->d.force[0];
-      q.fy = h->d.force[1];
-      q.fz = h->d.force[2];
-      std::memcpy(q.xyz, h->probe_xyz, sizeof(q.xyz));
-      q.out = h->probe_out + 3 * h->n_probes * h->probe_rows;
-      HIP_CHECK(h, launch_probes(q, h->d.store, h->stream), "probe kernel launch");
-      ++h->probe_rows;
-    }
+    if (int rc = step_once(h, plane, false)) return rc;
   }
   return STGLBM_OK;
 }

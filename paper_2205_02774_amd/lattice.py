@@ -121,6 +121,10 @@ class Lattice:
     def step(self, n=1):
         self._chk(self.lib.stglbm_step(self.handle, int(n)))
 
+    def step_noalloc(self, n=1):
+        """stglbm_step_noalloc: the same steps with the inlet planes staged in the library's static scratch."""
+        self._chk(self.lib.stglbm_step_noalloc(self.handle, int(n)))
+
     def stats_reset(self):
         self._chk(self.lib.stglbm_stats_reset(self.handle))
 
