@@ -249,44 +249,105 @@ def serving_mix(scale, budget_gib, max_active, chunk):
     srv = Server(int(budget_gib * 2 ** 30), max_active=max_active, chunk_steps=chunk,
                  executor=DeviceExecutor("cuda:0"))
     res, summ = srv.run(jobs)
-    summ.update({"step_scale": scale, "budget_gib": budget_gib, "max_active": max_active, "chunk_steps": chunk,
-                 "peak_active": srv.peak_active, "peak_gib": round(srv.peak_bytes / 2 ** 30, 2)})
+    queue = [r.admitted_s - r.arrival_s for r in res]
+    summ.update({"step_scale": scale, "budget_gib": round(budget_gib, 2), "max_active": max_active,
+                 "chunk_steps": chunk, "peak_active": srv.peak_active, "peak_gib": round(srv.peak_bytes / 2 ** 30, 2),
+                 "max_queue_s": float(max(queue)), "jobs_queued": int(sum(q > 0.05 for q in queue)),
+                 "cell_updates": int(sum(r.cells * r.steps for r in res if r.status == "ok"))})
     log(f"[bench] serving: {summ}")
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in summ.items()}
 
 
-def cpu_baseline(cfg, nz_sample, steps):
-    """Time the FP64 oracle on a spanwise slab of the same channel in a 1-thread subprocess."""
-    code = f"""
+def _cpu_info():
+    model = ""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
+_ORACLE_RUN = """
 import json, os, sys, time
-sys.path.insert(0, {ROOT!r})
+sys.path.insert(0, {root!r})
 from workloads import channel_config
 from oracle import OracleChannel
-cfg = channel_config({cfg['name']!r})
-cfg['nz'] = {nz_sample}
+cfg = channel_config({name!r})
+if {nz} > 0:
+    cfg['nz'] = {nz}
 cfg['cells'] = cfg['nx'] * cfg['ny'] * cfg['nz']
 ch = OracleChannel.from_config(cfg)
 ch.stats_reset()
-ch.step(1)
+ch.step({untimed})
 t0 = time.perf_counter()
 ch.step({steps})
 dt = time.perf_counter() - t0
 print(json.dumps({{"cells": cfg['cells'], "steps": {steps}, "seconds": dt}}))
 """
+
+
+def _oracle_procs(name, nz, steps, untimed, n_procs):
+    """Run n_procs independent 1-thread oracle processes at once; their timing records."""
     env = dict(os.environ, OMP_NUM_THREADS="1", MKL_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1")
-    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=900)
-    if res.returncode != 0:
-        log(res.stderr[-2000:])
+    code = _ORACLE_RUN.format(root=ROOT, name=name, nz=nz, steps=steps, untimed=untimed)
+    procs = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                              text=True, env=env) for _ in range(n_procs)]
+    recs = []
+    for p in procs:
+        out, err = p.communicate(timeout=900)
+        if p.returncode != 0:
+            log(err[-2000:])
+            return None
+        recs.append(json.loads(out.strip().splitlines()[-1]))
+    return recs
+
+
+def cpu_baseline(cfg, nz_sample, steps, all_core_max=16):
+    """The FP64 oracle on the host: one thread on a spanwise slab of the workload (the value),
+    the same slab in as many concurrent one-thread processes as the machine's CPU share allows
+    (at most `all_core_max`), and the 64x32x32 channel's 200 steps in full."""
+    model, nproc, usable = _cpu_info()
+    one = _oracle_procs(cfg["name"], nz_sample, steps, 1, 1)
+    if one is None:
         return None
-    rec = json.loads(res.stdout.strip().splitlines()[-1])
-    return {
+    rec = one[0]
+    n_all = max(1, min(usable, all_core_max))
+    t0 = time.perf_counter()
+    many = _oracle_procs(cfg["name"], nz_sample, steps, 1, n_all)
+    wall_all = time.perf_counter() - t0
+    small = _oracle_procs("channel-64x32x32", 0, 200, 0, 1)
+    out = {
         "value": rec["cells"] * rec["steps"] / rec["seconds"] / 1e6,
         "unit": "MLUPS",
         "cores": 1,
         "kind": "oracle",
         "sample": f"{cfg['nx']}x{cfg['ny']}x{nz_sample} spanwise slab of {cfg['name']} (same inlet), "
                   f"{steps} steps after 1 untimed, FP64 NumPy, 1 thread; {rec['seconds']:.1f} s",
+        "cpu_model": model,
+        "nproc": nproc,
+        "usable_cpus": usable,
     }
+    if many is not None:
+        cells_steps = sum(r["cells"] * r["steps"] for r in many)
+        slowest = max(r["seconds"] for r in many)
+        out["all_core"] = {"processes": n_all, "aggregate_mlups": round(cells_steps / slowest / 1e6, 3),
+                           "slowest_process_s": round(slowest, 2), "wall_s": round(wall_all, 2),
+                           "note": f"{n_all} concurrent one-thread oracle processes on the same slab "
+                                   f"(the box's CPU share for one GPU is {all_core_max} cores)"}
+    if small is not None:
+        r = small[0]
+        out["channel_64x32x32_200_steps"] = {"seconds": round(r["seconds"], 2),
+                                             "mlups": round(r["cells"] * r["steps"] / r["seconds"] / 1e6, 3),
+                                             "threads": 1}
+    log(f"[bench] cpu baseline: {out}")
+    return out
 
 
 def main():
@@ -300,9 +361,12 @@ def main():
     ap.add_argument("--lattice-variants", default="15:regularized,27:regularized,19:bgk",
                     help="velocity-set:operator pairs timed (FP32) on the same workload ('' = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-scale", type=float, default=0.05,
+    ap.add_argument("--serve-scale", type=float, default=1.0,
                     help="step budgets of the 64-job serving mix are scaled by this (1.0 = full mix; 0 = skip)")
-    ap.add_argument("--serve-budget-gib", type=float, default=24.0)
+    ap.add_argument("--serve-budget-gib", type=float, default=0.0,
+                    help="memory budget of the first serving leg (0 = 90 %% of the device's free memory)")
+    ap.add_argument("--serve-capped-gib", type=float, default=8.0,
+                    help="memory budget of the second serving leg, where admission binds (0 = skip)")
     ap.add_argument("--serve-max-active", type=int, default=16)
     ap.add_argument("--serve-chunk", type=int, default=250)
     ap.add_argument("--large", default="channel-1024x256x512-f16", help="large lattice timed after the main one ('' = skip)")
@@ -367,8 +431,14 @@ def main():
     adaptation = adaptation_study(cfg, args.adaptation_steps, 20000) if args.adaptation_steps > 0 else None
     serving = None
     if args.serve_scale > 0:
-        serving = serving_mix(args.serve_scale, args.serve_budget_gib, args.serve_max_active, args.serve_chunk)
+        budget = args.serve_budget_gib or 0.9 * torch.cuda.mem_get_info(0)[0] / 2 ** 30
+        serving = {"hbm_budget": serving_mix(args.serve_scale, budget, args.serve_max_active, args.serve_chunk)}
+        if args.serve_capped_gib > 0:
+            serving["capped_budget"] = serving_mix(args.serve_scale, args.serve_capped_gib, args.serve_max_active,
+                                                   args.serve_chunk)
     traffic = measured_traffic(args.workload, cfg["store"])
+    for v, rec in variants.items():
+        rec["traffic"] = measured_traffic(args.workload, v)
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, args.cpu_nz, args.cpu_steps)
     line = {
         "metric": "MLUPS + % HBM roofline (FP32 vs FP16-store STG-LBM); p50/p99 job latency",

@@ -122,6 +122,13 @@ const char* stglbm_status_string(int status);
 int stglbm_derive_units(double delta, int32_t ny, double u_b_lb, double U_b, double nu_phys,
                         double* c_x, double* c_t, double* nu_lb);
 
+/* Guo volume acceleration in lattice units from a physical one (m/s^2):
+ * F = a c_t^2 / c_x, the acceleration unit of eq. c_factor (the paper's
+ * periodic reference channel: 1 m/s^2 becomes 3.086e-8 at its resolution).
+ * a_phys and force_lb are host arrays of 3 doubles.  FP64 host arithmetic.
+ * E_INVAL for null arrays or non-positive c_x, c_t. */
+int stglbm_acceleration_to_lattice(double c_x, double c_t, const double* a_phys, double* force_lb);
+
 /* Bytes of device workspace a lattice needs (256-byte aligned pieces). */
 int stglbm_footprint(const stglbm_lattice_desc* desc, uint64_t* bytes);
 
@@ -207,6 +214,11 @@ int stglbm_set_f(stglbm_t h, const double* h_in, uint64_t n);
  * Used to start a run from a velocity profile (e.g. the periodic reference
  * channel).  n must be 3*NX*NY*NZ.  Synchronizes. */
 int stglbm_set_equilibrium(stglbm_t h, const double* h_u, uint64_t n);
+
+/* stglbm_set_equilibrium with a physical velocity field (m/s), converted on
+ * the device to lattice units by u c_t / c_x (eq. u_transfer) in FP64 before
+ * f_eq is formed.  E_INVAL for non-positive c_x, c_t or a wrong n. */
+int stglbm_set_equilibrium_physical(stglbm_t h, const double* h_u, uint64_t n, double c_x, double c_t);
 
 /* Velocity probes (adaptation diagnostics: time series at chosen cells).
  * After every following step the velocity the collision used at each of the

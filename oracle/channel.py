@@ -67,8 +67,7 @@ class OracleChannel:
         ch = cls(cfg["nx"], cfg["ny"], cfg["nz"], nu_lb=nu_lb, cs_smag=cfg["cs_smag"], force=force,
                  periodic_x=True)
         ch.c_x, ch.c_t = c_x, c_t
-        u0 = cfg["u_b_lb"] * np.asarray(cfg["start_perturbation"], dtype=np.float64)
-        u0[0] += units.velocity_to_lattice(rans["U3"][:, 0], c_t, c_x)[None, :, None]
+        u0 = units.velocity_to_lattice(np.asarray(cfg["start_velocity_phys"], dtype=np.float64), c_t, c_x)
         ch.set_f(L.equilibrium(np.ones(u0.shape[1:]), u0))
         return ch
 

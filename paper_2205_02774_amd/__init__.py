@@ -8,4 +8,5 @@ serving loop batches several channels on one device.
 
 from .abi import StglbmError, load as load_library, LIB_PATH  # noqa: F401
 from .lattice import (Lattice, channel_from_config, periodic_channel_from_config, derive_units,  # noqa: F401
+                      acceleration_to_lattice,
                       footprint, make_desc)

@@ -71,6 +71,8 @@ _SIGS = {
     "stglbm_set_f": (c_int32, [c_void_p, P_double, c_uint64]),
     "stglbm_get_f_planes": (c_int32, [c_void_p, c_int32, c_int32, P_double, c_uint64]),
     "stglbm_set_equilibrium": (c_int32, [c_void_p, P_double, c_uint64]),
+    "stglbm_set_equilibrium_physical": (c_int32, [c_void_p, P_double, c_uint64, c_double, c_double]),
+    "stglbm_acceleration_to_lattice": (c_int32, [c_double, c_double, P_double, P_double]),
     "stglbm_set_probes": (c_int32, [c_void_p, c_int32, ctypes.POINTER(c_int32), c_void_p, c_int64]),
     "stglbm_probe_rows": (c_int32, [c_void_p, ctypes.POINTER(c_int64)]),
     "stglbm_state_view": (c_int32, [c_void_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_uint64)]),

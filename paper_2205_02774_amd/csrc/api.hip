@@ -477,6 +477,14 @@ int stglbm_derive_units(double delta, int32_t ny, double u_b_lb, double U_b, dou
   return STGLBM_OK;
 }
 
+int stglbm_acceleration_to_lattice(double c_x, double c_t, const double* a_phys, double* force_lb) {
+  if (!a_phys || !force_lb) return fail(nullptr, STGLBM_E_INVAL, "acceleration_to_lattice: null array");
+  if (!(c_x > 0.0) || !(c_t > 0.0) || !std::isfinite(c_x) || !std::isfinite(c_t))
+    return fail(nullptr, STGLBM_E_INVAL, "acceleration_to_lattice: c_x and c_t must be positive");
+  for (int a = 0; a < 3; ++a) force_lb[a] = a_phys[a] * c_t * c_t / c_x;
+  return STGLBM_OK;
+}
+
 int stglbm_footprint(const stglbm_lattice_desc* desc, uint64_t* bytes) {
   if (const char* m = check_desc(desc)) return fail(nullptr, STGLBM_E_INVAL, m);
   if (!bytes) return fail(nullptr, STGLBM_E_INVAL, "null output");
@@ -767,8 +775,9 @@ int stglbm_set_f(stglbm_t h, const double* h_in, uint64_t n) {
   return STGLBM_OK;
 }
 
-int stglbm_set_equilibrium(stglbm_t h, const double* h_u, uint64_t n) {
-  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+namespace {
+
+int set_equilibrium_scaled(stglbm_t h, const double* h_u, uint64_t n, double scale) {
   const uint64_t total = 3ull * h->cells();
   if (!h_u || n != total) return fail(h, STGLBM_E_INVAL, "u buffer must hold 3*NX*NY*NZ doubles");
   const int rc = sync_and_check(h);
@@ -776,11 +785,26 @@ int stglbm_set_equilibrium(stglbm_t h, const double* h_u, uint64_t n) {
   // staged in the idle distribution buffer (Q s >= 30 >= 24 bytes per cell for every set and store)
   double* stage = static_cast<double*>(h->gbuf(1 - h->cur));
   HIP_CHECK(h, hipMemcpyAsync(stage, h_u, total * sizeof(double), hipMemcpyHostToDevice, h->stream), "hipMemcpyAsync u");
-  HIP_CHECK(h, launch_equilibrium(stage, h->d.store, h->q(), h->d.nx, h->d.ny, h->d.nz, h->gbuf(h->cur), h->stream),
+  HIP_CHECK(h, launch_equilibrium(stage, scale, h->d.store, h->q(), h->d.nx, h->d.ny, h->d.nz, h->gbuf(h->cur),
+                                  h->stream),
             "equilibrium kernel");
   HIP_CHECK(h, launch_fill_zero(h->at<char>(h->L.flag), kAlign, h->stream), "flag reset");
   HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   return STGLBM_OK;
+}
+
+}  // namespace
+
+int stglbm_set_equilibrium(stglbm_t h, const double* h_u, uint64_t n) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  return set_equilibrium_scaled(h, h_u, n, 1.0);
+}
+
+int stglbm_set_equilibrium_physical(stglbm_t h, const double* h_u, uint64_t n, double c_x, double c_t) {
+  if (!h) return fail(nullptr, STGLBM_E_INVAL, "null handle");
+  if (!(c_x > 0.0) || !(c_t > 0.0) || !std::isfinite(c_x) || !std::isfinite(c_t))
+    return fail(h, STGLBM_E_INVAL, "c_x and c_t must be positive");
+  return set_equilibrium_scaled(h, h_u, n, c_t / c_x);
 }
 
 static int copy_out(stglbm_t h, uint64_t off, uint64_t bytes, double* out) {

@@ -98,12 +98,13 @@ __global__ void import_f_kernel(const double* f, long long offset, long long cou
 // f = f_eq(rho = 1, u) (eq. local_eq) from a velocity field u[3][NZ][NY][NX]
 // in lattice units, computed in FP64 and rounded once to the store type.
 template <class Codec, int QN>
-__global__ void equilibrium_kernel(const double* u, int nx, int ny, int nz, typename Codec::storage* g) {
+__global__ void equilibrium_kernel(const double* u, double scale, int nx, int ny, int nz,
+                                   typename Codec::storage* g) {
   const long long plane2d = (long long)nx * ny;
   const long long cells = plane2d * nz;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += stride) {
-    const double ux = u[c], uy = u[cells + c], uz = u[2 * cells + c];
+    const double ux = scale * u[c], uy = scale * u[cells + c], uz = scale * u[2 * cells + c];
     const double uu = ux * ux + uy * uy + uz * uz;
     const long long z = c / plane2d, yx = c - z * plane2d;
     for (int i = 0; i < QN; ++i) {
@@ -243,11 +244,12 @@ hipError_t launch_import_f(const double* f, int store, int q, long long offset, 
   });
 }
 
-hipError_t launch_equilibrium(const double* u, int store, int q, int nx, int ny, int nz, void* g, hipStream_t s) {
+hipError_t launch_equilibrium(const double* u, double scale, int store, int q, int nx, int ny, int nz, void* g,
+                              hipStream_t s) {
   const int grid = grid_for(static_cast<unsigned long long>(nx) * ny * nz, 256);
   return by_store_and_set(store, q, [&](auto codec, auto qn) {
     using C = decltype(codec);
-    equilibrium_kernel<C, decltype(qn)::value><<<grid, 256, 0, s>>>(u, nx, ny, nz,
+    equilibrium_kernel<C, decltype(qn)::value><<<grid, 256, 0, s>>>(u, scale, nx, ny, nz,
                                                                      static_cast<typename C::storage*>(g));
     return hipGetLastError();
   });

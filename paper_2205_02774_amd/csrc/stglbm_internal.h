@@ -115,7 +115,9 @@ hipError_t launch_export_planes(const void* g, int store, int q, int nx, int ny,
                                 long long offset, long long count, double* out, hipStream_t s);
 hipError_t launch_import_f(const double* f, int store, int q, long long offset, long long count, int nz,
                            long long plane2d, void* g, hipStream_t s);
-hipError_t launch_equilibrium(const double* u, int store, int q, int nx, int ny, int nz, void* g, hipStream_t s);
+// f_eq(1, scale * u), u component-major [3][NZ][NY][NX] (scale: unit conversion, 1 for lattice units).
+hipError_t launch_equilibrium(const double* u, double scale, int store, int q, int nx, int ny, int nz, void* g,
+                              hipStream_t s);
 hipError_t launch_probes(const ProbeParams& p, int store, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, unsigned long long bytes, hipStream_t s);
 

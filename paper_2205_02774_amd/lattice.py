@@ -26,6 +26,17 @@ def derive_units(delta, ny, u_b_lb, U_b, nu_phys):
     return cx.value, ct.value, nu.value
 
 
+def acceleration_to_lattice(a_phys, c_x, c_t):
+    """Guo acceleration in lattice units of a physical acceleration (library call)."""
+    lib = abi.load()
+    a = np.ascontiguousarray(a_phys, dtype=np.float64)
+    if a.shape != (3,):
+        raise ValueError("a_phys must hold 3 components")
+    out = np.empty(3)
+    abi.check(lib.stglbm_acceleration_to_lattice(c_x, c_t, _dptr(a), _dptr(out)))
+    return tuple(float(v) for v in out)
+
+
 def make_desc(nx, ny, nz, *, nu_lb, store="f32", periodic_x=False, cs_smag=0.1, force=(0.0, 0.0, 0.0),
               rho_out=1.0, sponge_cells=0, sponge_K=1000.0, sponge_p=3.0, max_modes=0, max_rans=0,
               velocity_set=19, collision="regularized"):
@@ -175,6 +186,13 @@ class Lattice:
             raise ValueError("u must have shape (3, NZ, NY, NX)")
         self._chk(self.lib.stglbm_set_equilibrium(self.handle, _dptr(u), u.size))
 
+    def set_equilibrium_physical(self, u, c_x, c_t):
+        """f_eq(1, u c_t / c_x) for a physical velocity field u (3, NZ, NY, NX), converted by the library."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        if u.shape != (3, self.nz, self.ny, self.nx):
+            raise ValueError("u must have shape (3, NZ, NY, NX)")
+        self._chk(self.lib.stglbm_set_equilibrium_physical(self.handle, _dptr(u), u.size, float(c_x), float(c_t)))
+
     def set_probes(self, cells, capacity):
         """Record u at `cells` ((x, y, z) triples, at most 64) after each of the next `capacity` steps.
 
@@ -281,17 +299,15 @@ def channel_from_config(cfg, *, store=None, device="cuda", stream=None, periodic
 def periodic_channel_from_config(cfg, *, store=None, device="cuda", stream=None):
     """Build the force-driven periodic reference channel of a `workloads.periodic_channel` configuration.
 
-    Units come from the library (`stglbm_derive_units`); the physical
-    acceleration and the start velocity are converted with them (a = F c_t^2 / c_x,
-    u = u_phys c_t / c_x) and the start state is f_eq of that velocity.
+    Units come from the library: `stglbm_derive_units`, the body force from the
+    physical acceleration by `stglbm_acceleration_to_lattice`, and the start state
+    f_eq of the physical start velocity by `stglbm_set_equilibrium_physical`.
     """
     rans = cfg["rans"]
     c_x, c_t, nu_lb = derive_units(cfg["delta"], cfg["ny"], cfg["u_b_lb"], rans["U_b"], cfg["nu_phys"])
-    force = tuple(a * c_t * c_t / c_x for a in cfg["force_phys"])
+    force = acceleration_to_lattice(cfg["force_phys"], c_x, c_t)
     lat = Lattice(cfg["nx"], cfg["ny"], cfg["nz"], device=device, stream=stream, store=store or cfg["store"],
                   periodic_x=True, nu_lb=nu_lb, cs_smag=cfg["cs_smag"], force=force)
     lat.c_x, lat.c_t, lat.nu_lb, lat.force = c_x, c_t, nu_lb, force
-    u0 = cfg["u_b_lb"] * np.asarray(cfg["start_perturbation"], dtype=np.float64)
-    u0[0] += (rans["U3"][:, 0] * c_t / c_x)[None, :, None]
-    lat.set_equilibrium(u0)
+    lat.set_equilibrium_physical(cfg["start_velocity_phys"], c_x, c_t)
     return lat

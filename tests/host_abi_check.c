@@ -72,6 +72,16 @@ int main(void) {
   EXPECT(c_x > 0 && c_t > 0 && nu > 0);
   EXPECT(stglbm_derive_units(1.0, 0, 0.05, 15.37, 1.0 / 180.0, &c_x, &c_t, &nu) == STGLBM_E_INVAL);
 
+  /* the paper's worked example: c_x = 1/90 m, c_t = 1.852e-5 s, 1 m/s^2 -> F = 3.086e-8 */
+  const double acc[3] = {1.0, 0.0, -2.0};
+  double force[3] = {0, 0, 0};
+  EXPECT(stglbm_acceleration_to_lattice(1.0 / 90.0, 1.852e-5, acc, force) == STGLBM_OK);
+  EXPECT(force[0] > 3.085e-8 && force[0] < 3.087e-8 && force[1] == 0.0 && force[2] == -2.0 * force[0]);
+  EXPECT(stglbm_acceleration_to_lattice(0.0, 1.0, acc, force) == STGLBM_E_INVAL);
+  EXPECT(stglbm_acceleration_to_lattice(1.0, 1.0, NULL, force) == STGLBM_E_INVAL);
+  EXPECT(stglbm_step_noalloc(NULL, 1) == STGLBM_E_INVAL);
+  EXPECT(stglbm_set_equilibrium_physical(NULL, NULL, 0, 1.0, 1.0) == STGLBM_E_INVAL);
+
   /* init without a workspace, and calls on a null handle, fail before touching a device */
   stglbm_t h = (stglbm_t)0x1;
   EXPECT(stglbm_init_lattice(&d, NULL, 0, NULL, &h) == STGLBM_E_INVAL);

@@ -413,7 +413,7 @@ def test_laminar_inlet_outlet_steady_mass_flux():
 
 def test_periodic_reference_start_state():
     """The periodic reference channel starts from f_eq(1, u0): its moments return
-    rho = 1 and u0 exactly (equilibrium moments), u0 = RANS U(y) c_t/c_x + perturbation,
+    rho = 1 and u0 exactly (equilibrium moments), u0 = (RANS U(y) + perturbation) c_t/c_x,
     and the body force is a c_t^2/c_x for a = 1 m/s^2 (eq. of the unit conversion)."""
     from workloads import periodic_channel
     from oracle import units
@@ -422,8 +422,11 @@ def test_periodic_reference_start_state():
     rho = L.density(ch.f)
     u = np.einsum("ia,i...->a...", L.C.astype(np.float64), ch.f) / rho
     c_x, c_t, _, _ = units.channel_units(cfg["delta"], cfg["ny"], cfg["u_b_lb"], cfg["rans"]["U_b"], cfg["nu_phys"])
-    u0 = cfg["u_b_lb"] * cfg["start_perturbation"]
-    u0[0] += (cfg["rans"]["U3"][:, 0] * c_t / c_x)[None, :, None]
+    u0 = cfg["start_velocity_phys"] * c_t / c_x
+    # the perturbation is relative to the bulk velocity: U_b c_t/c_x is the lattice bulk velocity
+    pert = u0.copy()
+    pert[0] -= (cfg["rans"]["U3"][:, 0] * c_t / c_x)[None, :, None]
+    assert np.abs(pert).max() <= 0.1 * cfg["u_b_lb"] * (1 + 1e-12)
     np.testing.assert_allclose(rho, 1.0, atol=1e-14)
     np.testing.assert_allclose(u, u0, atol=1e-15)
     assert ch.force[0] == pytest.approx(c_t ** 2 / c_x, rel=1e-15)

@@ -80,7 +80,12 @@ def test_periodic_channel_config():
     b = periodic_channel(24, 16, 8, seed=3)
     assert a["periodic_x"] and a["sponge_cells"] == 0
     assert a["force_phys"] == (1.0, 0.0, 0.0)            # u_tau^2 / delta with u_tau = delta = 1
-    assert a["start_perturbation"].shape == (3, 8, 16, 24)
-    np.testing.assert_array_equal(a["start_perturbation"], b["start_perturbation"])
-    assert np.abs(a["start_perturbation"]).max() <= 0.1
+    u = a["start_velocity_phys"]
+    assert u.shape == (3, 8, 16, 24)
+    np.testing.assert_array_equal(u, b["start_velocity_phys"])
+    U_b = a["rans"]["U_b"]
+    pert = u.copy()
+    pert[0] -= a["rans"]["U3"][:, 0][None, :, None]
+    assert np.abs(pert).max() <= 0.1 * U_b
+    assert np.abs(pert).max() > 0.09 * U_b
     assert a["rans"]["U3"].shape[0] == 16

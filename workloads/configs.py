@@ -80,16 +80,19 @@ def periodic_channel(nx, ny, nz, re_tau=180.0, store="f32", seed=0, amplitude=0.
     body force in place of the inlet and outlet).  The force is the physical
     acceleration u_tau^2 / delta = 1 m/s^2 along x that balances the wall
     shear in the mean.  The start state is the RANS mean velocity at the
-    lattice rows plus a seeded perturbation: `start_perturbation` holds
-    uniform numbers in (-amplitude, amplitude) of shape (3, NZ, NY, NX), to be
-    scaled by the lattice bulk velocity.
+    lattice rows plus a seeded perturbation, in physical units:
+    `start_velocity_phys` (3, NZ, NY, NX) holds U(y) in the streamwise
+    component plus U_b times uniform numbers in (-amplitude, amplitude) in
+    every component.
     """
     cfg = dict(nx=nx, ny=ny, nz=nz, store=store, re_tau=re_tau, n_modes=0, alpha=0.0, seed=seed,
                name=f"periodic-{nx}x{ny}x{nz}", periodic_x=True)
     cfg["rans"] = _rans_on_rows(ny, re_tau)
     cfg["force_phys"] = (1.0, 0.0, 0.0)
     rng = np.random.default_rng(seed)
-    cfg["start_perturbation"] = rng.uniform(-amplitude, amplitude, size=(3, nz, ny, nx))
+    u = cfg["rans"]["U_b"] * rng.uniform(-amplitude, amplitude, size=(3, nz, ny, nx))
+    u[0] += cfg["rans"]["U3"][:, 0][None, :, None]
+    cfg["start_velocity_phys"] = u
     _common(cfg)
     cfg["sponge_cells"] = 0
     return cfg
