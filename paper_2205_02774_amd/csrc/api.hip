@@ -31,7 +31,8 @@ namespace {
 constexpr int kVersion = 10000;        // 1.0.0
 constexpr uint64_t kAlign = 256;
 constexpr uint32_t kCkptMagic = 0x5354474cu;   // "STGL"
-constexpr uint32_t kCkptVersion = 3;   // 2: store order [NZ][Q][NY][NX]; 3: velocity set and operator
+constexpr uint32_t kCkptVersion = 4;   // 2: store order [NZ][Q][NY][NX]; 3: velocity set and operator;
+                                       // 4: 16-bit stores keep FP64 totals and FP32 window sums
 
 thread_local std::string g_lib_error;
 
@@ -49,7 +50,7 @@ struct TraceRange {
 };
 
 struct Layout {
-  uint64_t g[2] = {0, 0}, stats = 0, sponge = 0, flag = 0, ubc = 0, rans = 0, rows = 0, modes = 0,
+  uint64_t g[2] = {0, 0}, stats = 0, win = 0, sponge = 0, flag = 0, ubc = 0, rans = 0, rows = 0, modes = 0,
            sqrtq = 0, bz = 0, sig = 0, scalars = 0, total = 0;
   int vec = 1, nxt = 0, wx = 1, wz = 1, nxg = 0, slots = 0, lw = 0, zstep = 1, nblocks = 0;
   bool short_chunks_when_idle = true;   // steps without statistics: their own shape
@@ -176,7 +177,17 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   const uint64_t gbytes = static_cast<uint64_t>(set_size(d)) * cells * store_bytes(d->store);
   L.g[0] = take(gbytes);
   L.g[1] = take(gbytes);
-  L.stats = take(static_cast<uint64_t>(L.slots) * 9 * d->nx * d->ny * sizeof(double));
+  // Statistics: FP32 stores keep FP64 sums per slot; 16-bit stores keep FP64
+  // totals and FP32 sums per slot over the current window (kStatsWindow
+  // sampled steps).  The two pieces are adjacent, before the sponge table.
+  const uint64_t bins9 = 9ull * d->nx * d->ny;
+  if (d->store == STGLBM_F32) {
+    L.stats = take(static_cast<uint64_t>(L.slots) * bins9 * sizeof(double));
+    L.win = L.stats;
+  } else {
+    L.stats = take(bins9 * sizeof(double));
+    L.win = take(static_cast<uint64_t>(L.slots) * bins9 * sizeof(float));
+  }
   L.sponge = take(static_cast<uint64_t>(d->nx) * sizeof(float));
   L.flag = take(2 * sizeof(int));
   if (!d->periodic_x) {
@@ -338,6 +349,8 @@ StepParams step_params(stglbm_t h) {
   p.sponge = h->at<float>(h->L.sponge);
   p.ubc = nullptr;   // set per step from the plane ring
   p.stats = h->at<double>(h->L.stats);
+  p.win = h->at<float>(h->L.win);
+  p.win_first = 0;
   p.flag = h->at<int>(h->L.flag);
   return p;
 }
@@ -395,6 +408,8 @@ int ring_plane(stglbm_t h, int64_t t, const float** plane) {
 int step_once(stglbm_t h, const float* plane, bool timed_ok) {
   StepParams p = step_params(h);
   p.ubc = plane;
+  const bool window = h->sampling && h->d.store != STGLBM_F32;
+  if (window) p.win_first = h->n_samples % kStatsWindow == 0 ? 1 : 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = timed_ok && h->prof && (h->prof_count++ % h->prof_every == 0);
   if (timed) {
@@ -410,6 +425,12 @@ int step_once(stglbm_t h, const float* plane, bool timed_ok) {
   h->cur = 1 - h->cur;
   ++h->t;
   if (h->sampling) ++h->n_samples;
+  if (window && h->n_samples % kStatsWindow == 0) {
+    // fold the window's FP32 slot sums into the FP64 totals, slots in order
+    HIP_CHECK(h, launch_stats_sum(nullptr, 0, h->at<float>(h->L.win), h->L.slots, 9ll * h->d.nx * h->d.ny,
+                                  h->at<double>(h->L.stats), true, h->stream),
+              "statistics fold");
+  }
   if (h->n_probes > 0 && h->probe_rows < h->probe_capacity) {
     ProbeParams q{};
     q.g = h->gbuf(h->cur);
@@ -696,15 +717,32 @@ int stglbm_get_stats(stglbm_t h, double* h_out, uint64_t n, int64_t* n_samples) 
   const uint64_t bins = static_cast<uint64_t>(h->d.nx) * h->d.ny;
   if (!h_out || n != bins * 9) return fail(h, STGLBM_E_INVAL, "stats buffer must hold NX*NY*9 doubles");
   const int rc = sync_and_check(h);
-  std::vector<double> raw(static_cast<size_t>(h->L.slots) * 9 * bins);
+  const bool f32 = h->d.store == STGLBM_F32;
+  const size_t n9 = 9 * bins;
+  std::vector<double> raw(f32 ? static_cast<size_t>(h->L.slots) * n9 : n9);
   HIP_CHECK(h, hipMemcpy(raw.data(), h->at<double>(h->L.stats), raw.size() * sizeof(double), hipMemcpyDeviceToHost),
             "hipMemcpy stats");
-  // device layout [slot][k][y][x]; API layout [x][y][k]; slots summed in order
+  std::vector<float> win(f32 ? 0 : static_cast<size_t>(h->L.slots) * n9);
+  if (!f32)
+    HIP_CHECK(h, hipMemcpy(win.data(), h->at<float>(h->L.win), win.size() * sizeof(float), hipMemcpyDeviceToHost),
+              "hipMemcpy window sums");
+  // device layout [slot][k][y][x]; API layout [x][y][k].  FP32 stores: the
+  // slots summed in order.  16-bit stores: the totals plus the current
+  // window's slots in order (the fold's own sum, so a later fold gives the same
+  // numbers whenever the statistics are read).
+  const bool open = !f32 && h->n_samples % kStatsWindow != 0;
   for (int x = 0; x < h->d.nx; ++x)
     for (int y = 0; y < h->d.ny; ++y)
       for (int k = 0; k < 9; ++k) {
+        const size_t e = static_cast<size_t>(k) * bins + static_cast<size_t>(y) * h->d.nx + x;
         double v = 0.0;
-        for (int s = 0; s < h->L.slots; ++s) v += raw[(static_cast<size_t>(s) * 9 + k) * bins + static_cast<size_t>(y) * h->d.nx + x];
+        if (f32) {
+          for (int s = 0; s < h->L.slots; ++s) v += raw[static_cast<size_t>(s) * n9 + e];
+        } else {
+          v = raw[e];
+          if (open)
+            for (int s = 0; s < h->L.slots; ++s) v += static_cast<double>(win[static_cast<size_t>(s) * n9 + e]);
+        }
         h_out[(static_cast<size_t>(x) * h->d.ny + y) * 9 + k] = v;
       }
   if (n_samples) *n_samples = h->n_samples;

@@ -24,6 +24,17 @@ __global__ void fill_zero_kernel(uint4* p, unsigned long long n16) {
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+__global__ void stats_sum_kernel(const double* d, int nd, const float* f, int nf, long long n, double* out,
+                                 bool add) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    double v = add ? out[e] : 0.0;
+    for (int k = 0; k < nd; ++k) v += d[k * n + e];
+    for (int k = 0; k < nf; ++k) v += static_cast<double>(f[k * n + e]);
+    out[e] = v;
+  }
+}
+
 __global__ void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, unsigned long long n16) {
   const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
   for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
@@ -187,6 +198,12 @@ hipError_t launch_step(const StepParams& p, int store, bool stats, hipStream_t s
     case 2: return launch_d3q19_regularized<CodecBF16>(p, stats, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_stats_sum(const double* d, int nd, const float* f, int nf, long long n, double* out, bool add,
+                            hipStream_t s) {
+  stats_sum_kernel<<<grid_for(static_cast<unsigned long long>(n), 256), 256, 0, s>>>(d, nd, f, nf, n, out, add);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(void* ptr, unsigned long long bytes, hipStream_t s) {

@@ -16,6 +16,8 @@
 #pragma once
 #include "stglbm_internal.h"
 
+#include <type_traits>
+
 namespace stglbm {
 namespace {
 
@@ -654,17 +656,23 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
     // LDS.  All 9 slot values are loaded first, before the barrier: a
     // read-modify-write per quantity would make 9 dependent round trips (the
     // stores may alias the later loads as far as the compiler knows).
+    // FP32 stores add to FP64 slot sums; 16-bit stores add to FP32 window
+    // sums (half the bytes), which the host folds into FP64 every
+    // kStatsWindow sampled steps.
+    using Acc = typename std::conditional<SB == 4, double, float>::type;
     extern __shared__ float red[];             // [wz][9][64 wx V]
     const int tx = threadIdx.x, bx = 64 * p.wx * V;
     const bool rmw = wz == 0 && active && wave_live;
     const long long sstride = (long long)ny * nx;
-    double* st = p.stats + (long long)slot * 9 * sstride + (long long)y * nx + x0;
-    double old[9][V];
+    Acc* const base = SB == 4 ? reinterpret_cast<Acc*>(p.stats) : reinterpret_cast<Acc*>(p.win);
+    Acc* st = base + (long long)slot * 9 * sstride + (long long)y * nx + x0;
+    const bool fresh = SB != 4 && p.win_first;
+    Acc old[9][V];
     if (rmw) {
 #pragma unroll
       for (int q = 0; q < 9; ++q)
 #pragma unroll
-        for (int k = 0; k < V; ++k) old[q][k] = st[q * sstride + k];
+        for (int k = 0; k < V; ++k) old[q][k] = fresh ? Acc(0) : st[q * sstride + k];
     }
     if (p.wz > 1) {
 #pragma unroll
@@ -680,7 +688,7 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
         for (int k = 0; k < V; ++k) {
           float v = acc[q][k];
           for (int w = 1; w < p.wz; ++w) v += red[(w * 9 + q) * bx + tx * V + k];
-          st[q * sstride + k] = old[q][k] + static_cast<double>(v);
+          st[q * sstride + k] = old[q][k] + static_cast<Acc>(v);
         }
     }
   }

@@ -57,9 +57,16 @@ struct StepParams {
   float mach_limit;         // inlet guard: |u_bc,x| < 0.3 c_s
   const float* sponge;      // [NX] viscosity multipliers (all 1 if no sponge)
   const float* ubc;         // [NY][NZ][3] inlet velocity of this step (lattice units)
-  double* stats;            // [slots][9][NY][NX] FP64 sums
+  double* stats;            // FP32 store: [slots][9][NY][NX] FP64 sums
+  float* win;               // 16-bit stores: [slots][9][NY][NX] FP32 sums of the current window
+  int win_first;            // 16-bit stores: first sampled step of a window (store, not add)
   int* flag;
 };
+
+// Statistics of 16-bit stores: every launch adds its per-slot sums to FP32
+// window sums; after kStatsWindow sampled steps (counted from stats_reset) they
+// are folded, in slot order, into the FP64 totals [9][NY][NX].
+constexpr int kStatsWindow = 16;
 
 // Velocity probes: after a step, u at up to kMaxProbes cells of the new state.
 constexpr int kMaxProbes = 64;
@@ -107,6 +114,10 @@ hipError_t launch_step_variant(const StepParams& p, int store, bool stats, hipSt
 hipError_t launch_stg(const StgParams& p, hipStream_t s);
 hipError_t launch_inlet_setup(const SetupParams& p, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, unsigned long long bytes, hipStream_t s);
+// out[e] = (add ? out[e] : 0) + sum_s d[s n + e] (s < nd) + sum_s f[s n + e] (s < nf),
+// FP64, in that order, for e < n.
+hipError_t launch_stats_sum(const double* d, int nd, const float* f, int nf, long long n, double* out, bool add,
+                            hipStream_t s);
 hipError_t launch_sponge(float* sponge, int nx, int cells, double K, double p, hipStream_t s);
 // Public order [Q][NZ][NY][NX] <-> stored order [NZ][Q][NY][NX].
 hipError_t launch_export_f(const void* g, int store, int q, long long offset, long long count, int nz,

@@ -111,15 +111,18 @@ def test_derive_units_matches_oracle(lib):
     ((64, 32, 32), "f16", 19, 32),       # capped at NZ
 ])
 def test_statistics_slots_of_the_launch_shape(lib, shape, store, qset, slots):
-    """The FP64 statistics slots the layout reserves follow the launch-shape
-    rule: periodic lattices hold the two distribution buffers, the slots and
-    under 1 MiB of small tables, so the slot count is read off the footprint."""
+    """The statistics slots the layout reserves follow the launch-shape rule:
+    periodic lattices hold the two distribution buffers, the statistics and
+    under 1 MiB of small tables, so the slot count is read off the footprint.
+    FP32 stores keep FP64 sums per slot; 16-bit stores keep one set of FP64
+    totals and FP32 window sums per slot."""
     from paper_2205_02774_amd import make_desc, footprint
     nx, ny, nz = shape
     fp = footprint(make_desc(nx, ny, nz, nu_lb=1e-3, store=store, periodic_x=True, velocity_set=qset))
     g = 2 * qset * nx * ny * nz * (4 if store == "f32" else 2)
-    bins = 9 * nx * ny * 8
-    assert slots * bins <= fp - g < slots * bins + 2 ** 20
+    bins = 9 * nx * ny
+    need = slots * bins * 8 if store == "f32" else bins * 8 + slots * bins * 4
+    assert need <= fp - g < need + 2 ** 20
 
 
 def test_velocity_set_and_collision_validation(lib):
