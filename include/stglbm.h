@@ -276,6 +276,15 @@ int stglbm_profile_read(stglbm_t h, double* out, uint64_t n);
  * calibration kernel for counter and roofline measurements. */
 int stglbm_copy_probe(const void* d_src, void* d_dst, uint64_t bytes, void* hip_stream);
 
+/* HBM bandwidth probes on a stream (measurement of the ceiling the step
+ * kernel is compared with): mode 0 the plain copy of stglbm_copy_probe; 1 a
+ * copy with four 16-byte loads in flight per lane and non-temporal stores;
+ * 2 a read-only sweep of d_src (d_dst may be null; if not, its first 16
+ * bytes receive the XOR of all words only when that equals one fixed 128-bit
+ * constant); 3 a write-only fill of d_dst (d_src may be null).  bytes is a
+ * multiple of 16.  E_INVAL for another mode or a missing buffer. */
+int stglbm_bandwidth_probe(const void* d_src, void* d_dst, uint64_t bytes, int32_t mode, void* hip_stream);
+
 /* Free the host handle (the workspace stays the caller's). */
 int stglbm_destroy(stglbm_t h);
 

@@ -89,6 +89,7 @@ _SIGS = {
     "stglbm_profile": (c_int32, [c_void_p, c_int32]),
     "stglbm_profile_read": (c_int32, [c_void_p, P_double, c_uint64]),
     "stglbm_copy_probe": (c_int32, [c_void_p, c_void_p, c_uint64, c_void_p]),
+    "stglbm_bandwidth_probe": (c_int32, [c_void_p, c_void_p, c_uint64, c_int32, c_void_p]),
     "stglbm_destroy": (c_int32, [c_void_p]),
     "stglbm_last_error": (ctypes.c_char_p, [c_void_p]),
 }

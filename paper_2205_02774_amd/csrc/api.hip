@@ -51,7 +51,7 @@ struct TraceRange {
 
 struct Layout {
   uint64_t g[2] = {0, 0}, stats = 0, win = 0, sponge = 0, flag = 0, ubc = 0, rans = 0, rows = 0, modes = 0,
-           sqrtq = 0, bz = 0, sig = 0, scalars = 0, total = 0;
+           sqrtq = 0, arow = 0, bz = 0, sig = 0, scalars = 0, total = 0;
   int vec = 1, nxt = 0, wx = 1, wz = 1, nxg = 0, slots = 0, lw = 0, zstep = 1, nblocks = 0;
   bool short_chunks_when_idle = true;   // steps without statistics: their own shape
   int wx_idle = 1, nxg_idle = 1, lw_idle = 1;
@@ -196,6 +196,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
     L.rows = take(static_cast<uint64_t>(d->ny) * kRowFields * sizeof(double));
     L.modes = take(static_cast<uint64_t>(d->max_modes) * kModeFields * sizeof(double));
     L.sqrtq = take(static_cast<uint64_t>(d->ny) * d->max_modes * sizeof(double));
+    L.arow = take(static_cast<uint64_t>(d->ny) * d->max_modes * 2 * sizeof(double));
     L.bz = take(static_cast<uint64_t>(d->max_modes) * d->nz * sizeof(float2));
     L.sig = take(static_cast<uint64_t>(d->max_modes) * sizeof(float4));
     L.scalars = take(kScalars * sizeof(double));
@@ -360,7 +361,7 @@ StepParams step_params(stglbm_t h) {
 int launch_planes(stglbm_t h, int64_t t_first, int n, float* out, bool timed_ok = true) {
   StgParams s{};
   s.modes = h->at<double>(h->L.modes);
-  s.sqrtq = h->at<double>(h->L.sqrtq);
+  s.arow = h->at<double2>(h->L.arow);
   s.bz = h->at<float2>(h->L.bz);
   s.sig = h->at<float4>(h->L.sig);
   s.rows = h->at<double>(h->L.rows);
@@ -588,6 +589,7 @@ int stglbm_set_rans_inlet(stglbm_t h, const stglbm_rans_inlet* in) {
   p.rows = h->at<double>(h->L.rows);
   p.modes = h->at<double>(h->L.modes);
   p.sqrtq = h->at<double>(h->L.sqrtq);
+  p.arow = h->at<double2>(h->L.arow);
   p.bz = h->at<float2>(h->L.bz);
   p.sig = h->at<float4>(h->L.sig);
   p.scalars = h->at<double>(h->L.scalars);
@@ -987,6 +989,14 @@ int stglbm_copy_probe(const void* d_src, void* d_dst, uint64_t bytes, void* hip_
   if (!d_src || !d_dst || bytes % 16) return fail(nullptr, STGLBM_E_INVAL, "copy_probe needs non-null buffers and bytes % 16 == 0");
   const hipError_t e = launch_copy(d_src, d_dst, bytes, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return fail(nullptr, STGLBM_E_HIP, std::string("copy kernel: ") + hipGetErrorString(e));
+  return STGLBM_OK;
+}
+
+int stglbm_bandwidth_probe(const void* d_src, void* d_dst, uint64_t bytes, int32_t mode, void* hip_stream) {
+  if ((mode != 3 && !d_src) || (mode != 2 && !d_dst) || bytes % 16 || mode < 0 || mode > 3)
+    return fail(nullptr, STGLBM_E_INVAL, "bandwidth_probe needs mode 0..3, the buffers it uses and bytes % 16 == 0");
+  const hipError_t e = launch_bandwidth_probe(d_src, d_dst, bytes, mode, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(nullptr, STGLBM_E_HIP, std::string("bandwidth probe: ") + hipGetErrorString(e));
   return STGLBM_OK;
 }
 

@@ -12,9 +12,10 @@
 // and the spanwise phasor table exp(i k^n d^n_z z).
 //
 // Plane (steps 5-8): the phase k^n d^n . x' + phi^n of eq. psu splits into a
-// row part k^n d^n_y y_j + phi^n + 2 pi d^n_x (x_in - U_b t)/L_e, evaluated in
-// FP64 per (row, mode, step), and a spanwise part k^n d^n_z z held as an FP32
-// phasor.  Their product gives cos of the full phase without a large-argument
+// row part k^n d^n_y y_j + phi^n + 2 pi d^n_x (x_in - U_b t)/L_e and a spanwise
+// part k^n d^n_z z held as an FP32 phasor.  The row part's exponential is the
+// product, in FP64, of a stored time-independent phasor (row, mode) and the
+// time factor (mode, step), rounded once to FP32.  Their product gives cos of the full phase without a large-argument
 // FP32 cosine.  A block owns 1 to 8 rows and 64 spanwise nodes of one plane
 // (one launch makes the planes of up to 16 steps); its 8 waves split the
 // modes, the row phasors and sigma^n are staged in LDS per chunk of modes,
@@ -203,6 +204,21 @@ __global__ __launch_bounds__(256) void inlet_spectrum_kernel(SetupParams p) {
   for (int m = tid; m < p.n_modes; m += blockDim.x) q[m] = sqrt(q[m] / total);
 }
 
+// Row phasors sqrt 6 sqrt(q^n) exp(i (k^n d^n_y y_j + phi^n)), y_j = (j + 1/2) c_x:
+// the part of the plane's phase that does not change with time, FP64.
+__global__ void inlet_rowphase_kernel(SetupParams p) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)p.n_modes * p.ny) return;
+  const int j = static_cast<int>(e / p.n_modes);
+  const int m = static_cast<int>(e % p.n_modes);
+  const double* md = p.modes + (long long)m * kModeFields;
+  const double sqrt6 = 2.449489742783178098;
+  double s, c;
+  sincos(md[0] * md[2] * ((j + 0.5) * p.c_x) + md[7], &s, &c);
+  const double a = sqrt6 * p.sqrtq[e];
+  p.arow[e] = make_double2(a * c, a * s);
+}
+
 // Spanwise phasors exp(i k^n d^n_z z_k), z_k = k c_x, FP64 -> FP32.
 __global__ void inlet_zphase_kernel(SetupParams p) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -240,34 +256,39 @@ __global__ __launch_bounds__(64 * kStgWaves) void stg_plane_kernel(StgParams p) 
   // Modes staged per pass; the row phasors and sigma of the last pass are dead
   // when the partial sums meet, so the two share LDS (under 64 KiB per block).
   constexpr int kChunk = kStgChunk * 2 / (kStgRows >= 2 ? kStgRows : 2);
-  constexpr int kStageBytes = kStgRows * kChunk * 8 + kChunk * 16;
+  constexpr int kStageBytes = kStgRows * kChunk * 8 + kChunk * 16 + kChunk * 16;
   constexpr int kRedBytes = kStgWaves * 3 * kStgRows * 64 * 4;
   __shared__ __attribute__((aligned(16))) char smem[kStageBytes > kRedBytes ? kStageBytes : kRedBytes];
   float2 (*P)[kChunk] = reinterpret_cast<float2 (*)[kChunk]>(smem);
   float4* SG = reinterpret_cast<float4*>(smem + kStgRows * kChunk * 8);
+  double2* G = reinterpret_cast<double2*>(smem + kStgRows * kChunk * 8 + kChunk * 16);
   float (*red)[3 * kStgRows][64] = reinterpret_cast<float (*)[3 * kStgRows][64]>(smem);
-  const double sqrt6 = 2.449489742783178098;
   float v[kStgRows][3];
 #pragma unroll
   for (int r = 0; r < kStgRows; ++r) v[r][0] = v[r][1] = v[r][2] = 0.f;
   for (int base = 0; base < p.n_modes; base += kChunk) {
     const int cnt = min(kChunk, p.n_modes - base);
+    // time part of the phase, per mode: exp(i 2 pi d_x (x_in - U_b t) / L_e)
+    for (int m = tid; m < cnt; m += 64 * kStgWaves) {
+      double sn, cs;
+      sincos(p.modes[(long long)(base + m) * kModeFields + 1] * tphase, &sn, &cs);
+      G[m] = make_double2(cs, sn);
+      SG[m] = p.sig[base + m];
+    }
+    __syncthreads();
+    // P = sqrt 6 sqrt(q) exp(i psi_row) of the full row part: the stored
+    // time-independent phasor times the time part, in FP64, rounded once
     for (int e = tid; e < kStgRows * cnt; e += 64 * kStgWaves) {
       const int r = e / cnt, m = e - r * cnt;
       const int j = j0 + r;
       float2 ph = make_float2(0.f, 0.f);
       if (j < p.ny) {
-        const double* md = p.modes + (long long)(base + m) * kModeFields;
-        // row part of the phase: k d_y y_j + phi + 2 pi d_x (x_in - U_b t) / L_e
-        const double psi = md[0] * md[2] * ((j + 0.5) * p.c_x) + md[7] + md[1] * tphase;
-        double sn, cs;
-        sincos(psi, &sn, &cs);
-        const double a = sqrt6 * p.sqrtq[(long long)j * p.n_modes + base + m];
-        ph = make_float2(static_cast<float>(a * cs), static_cast<float>(a * sn));
+        const double2 a = p.arow[(long long)j * p.n_modes + base + m];
+        const double2 g = G[m];
+        ph = make_float2(static_cast<float>(a.x * g.x - a.y * g.y), static_cast<float>(a.x * g.y + a.y * g.x));
       }
       P[r][m] = ph;
     }
-    for (int m = tid; m < cnt; m += 64 * kStgWaves) SG[m] = p.sig[base + m];
     __syncthreads();
     const float2* bz = p.bz + (long long)base * p.nz + zc;
     const long long step = (long long)kStgWaves * p.nz;
@@ -345,6 +366,10 @@ hipError_t launch_inlet_setup(const SetupParams& p, hipStream_t s) {
   if (e != hipSuccess) return e;
   const long long n = (long long)p.n_modes * p.nz;
   inlet_zphase_kernel<<<static_cast<unsigned>((n + 255) / 256), 256, 0, s>>>(p);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long nr = (long long)p.n_modes * p.ny;
+  inlet_rowphase_kernel<<<static_cast<unsigned>((nr + 255) / 256), 256, 0, s>>>(p);
   return hipGetLastError();
 }
 

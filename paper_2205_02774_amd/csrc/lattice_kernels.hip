@@ -41,6 +41,53 @@ __global__ void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ d
     dst[i] = src[i];
 }
 
+// Bandwidth probes: U independent 16-byte loads in flight per lane before
+// the stores (non-temporal), a read-only sweep (the XOR of what it read is
+// stored only if it equals a value no buffer here holds), a write-only fill.
+using U4 = unsigned __attribute__((ext_vector_type(4)));
+
+template <int U>
+__global__ void copy_wide_kernel(const U4* __restrict__ src, U4* __restrict__ dst, unsigned long long n16) {
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + (U - 1) * stride < n16; i += U * stride) {
+    U4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = src[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) __builtin_nontemporal_store(v[u], &dst[i + u * stride]);
+  }
+  for (; i < n16; i += stride) dst[i] = src[i];
+}
+
+template <int U>
+__global__ void read_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, unsigned long long n16) {
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+  uint4 acc = make_uint4(0u, 0u, 0u, 0u);
+  for (; i + (U - 1) * stride < n16; i += U * stride) {
+    uint4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = src[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      acc.x ^= v[u].x; acc.y ^= v[u].y; acc.z ^= v[u].z; acc.w ^= v[u].w;
+    }
+  }
+  for (; i < n16; i += stride) {
+    const uint4 v = src[i];
+    acc.x ^= v.x; acc.y ^= v.y; acc.z ^= v.z; acc.w ^= v.w;
+  }
+  if (dst && acc.x == 0x9e3779b9u && acc.y == 0x7f4a7c15u && acc.z == 0xf39cc060u && acc.w == 0x5cedc834u) dst[0] = acc;
+}
+
+__global__ void write_kernel(U4* __restrict__ dst, unsigned long long n16) {
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  const U4 one = {1u, 1u, 1u, 1u};
+  for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    __builtin_nontemporal_store(one, &dst[i]);
+}
+
 // Sponge (eq. sponge_visco): nu_sponge = nu_eff (1 + K s^p), s = (x - x_s)/(x_e - x_s),
 // x_e = NX - 1, x_s = x_e - L_s; stored as the multiplier of tau - 1/2.
 __global__ void sponge_kernel(float* sponge, int nx, int cells, double K, double pw) {
@@ -219,6 +266,24 @@ hipError_t launch_copy(const void* src, void* dst, unsigned long long bytes, hip
   const unsigned long long n16 = bytes / 16;
   if (n16 == 0) return hipSuccess;
   copy_kernel<<<grid_for(n16, 256), 256, 0, s>>>(static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_bandwidth_probe(const void* src, void* dst, unsigned long long bytes, int mode, hipStream_t s) {
+  if (bytes % 16 || mode < 0 || mode > 3) return hipErrorInvalidValue;
+  const unsigned long long n16 = bytes / 16;
+  if (n16 == 0) return hipSuccess;
+  // one pass over the data: 4 elements per lane for modes 1 and 2, one for 0 and 3
+  // (grids that loop several times over a resident set of blocks streamed slower)
+  const auto* in = static_cast<const uint4*>(src);
+  auto* out = static_cast<uint4*>(dst);
+  const int g4 = grid_for((n16 + 3) / 4, 256);
+  switch (mode) {
+    case 0: copy_kernel<<<grid_for(n16, 256), 256, 0, s>>>(in, out, n16); break;
+    case 1: copy_wide_kernel<4><<<g4, 256, 0, s>>>(reinterpret_cast<const U4*>(in), reinterpret_cast<U4*>(out), n16); break;
+    case 2: read_kernel<4><<<g4, 256, 0, s>>>(in, out, n16); break;
+    default: write_kernel<<<grid_for(n16, 256), 256, 0, s>>>(reinterpret_cast<U4*>(out), n16); break;
+  }
   return hipGetLastError();
 }
 

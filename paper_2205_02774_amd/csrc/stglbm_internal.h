@@ -82,7 +82,7 @@ struct ProbeParams {
 // STG inlet plane, one launch per time step.
 struct StgParams {
   const double* modes;      // [N][8]
-  const double* sqrtq;      // [NY][N]
+  const double2* arow;      // [NY][N] sqrt 6 sqrt(q^n) exp(i (k^n d^n_y y_j + phi^n))
   const float2* bz;         // [N][NZ] spanwise phasors exp(i k d_z z)
   const float4* sig;        // [N] sigma^n in FP32 (x, y, z, 0)
   const double* rows;       // [NY][18]
@@ -103,6 +103,7 @@ struct SetupParams {
   double* rows;             // [NY][18]
   double* modes;            // [N][8]
   double* sqrtq;            // [NY][N]
+  double2* arow;            // [NY][N] time-independent row phasors of the plane kernel
   float2* bz;               // [N][NZ]
   float4* sig;              // [N]
   double* scalars;          // [8]
@@ -131,5 +132,8 @@ hipError_t launch_equilibrium(const double* u, double scale, int store, int q, i
                               hipStream_t s);
 hipError_t launch_probes(const ProbeParams& p, int store, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, unsigned long long bytes, hipStream_t s);
+// mode 0: the plain copy; 1: copy with 4 x 16 B loads in flight per lane and non-temporal
+// stores; 2: read-only sweep of src (dst unchanged); 3: write-only fill of dst.
+hipError_t launch_bandwidth_probe(const void* src, void* dst, unsigned long long bytes, int mode, hipStream_t s);
 
 }  // namespace stglbm
