@@ -279,7 +279,7 @@ def test_full_size_front_parity(cfg_index, steps):
     lat.close()
 
 
-@pytest.mark.parametrize("cfg_index,qset,steps", [(1, 19, 8), (1, 27, 8), (2, 19, 8), (3, 19, 4)])
+@pytest.mark.parametrize("cfg_index,qset,steps", [(1, 19, 8), (1, 27, 8), (2, 19, 8), (2, 19, 20), (3, 19, 4)])
 def test_full_size_statistics_front_parity(cfg_index, qset, steps):
     """FP64 statistics of the full-size channels in the bench's launch shapes.
 
@@ -287,7 +287,8 @@ def test_full_size_statistics_front_parity(cfg_index, qset, steps):
     wave: FP32 D3Q19 (whole-row blocks of two z waves, 128-row chunks, 2 FP64
     slots), FP32 D3Q27 (one z wave, 64-row chunks, 4 slots) and FP16 (one z
     wave; 16-row chunks and 16 slots at 512x128x256, 128-row chunks and 4
-    slots at 1024x256x512).  From rest, after K sampled steps the bins
+    slots at 1024x256x512; FP32 window sums folded into FP64 after the 16th
+    sampled step, which the 20-step case crosses).  From rest, after K sampled steps the bins
     x <= K match an oracle channel of 2K + 2 planes with the same inlet (as in
     the front test above), and every bin beyond K sums a velocity that is
     exactly zero.  FP32: the 1e-6 bar.  FP16: each step's rounding of g moves
@@ -420,13 +421,22 @@ def test_half_store_rounding_ties():
         assert even.all() and np.array_equal(back, want)
 
 
-def test_determinism_and_checkpoint_restore():
+@pytest.mark.parametrize("store", ["f32", "f16", "bf16"])
+def test_determinism_and_checkpoint_restore(store):
+    """Bitwise: two runs agree, and a run restored from a checkpoint continues
+    exactly.  16-bit stores keep statistics as FP32 sums over windows of 16
+    sampled steps folded into FP64: 60 steps cross three folds, the checkpoint
+    at 30 falls inside a window, and reading the statistics mid-window must
+    not change what is read later."""
     cfg = channel_config(0)
+    cfg["store"] = store
     a = _lat(cfg)
     a.stats_reset()
     a.step(30)
     ck = a.checkpoint()
-    a.step(30)
+    a.step(7)
+    a.get_stats()
+    a.step(23)
     fa, sa = a.get_f(), a.get_stats()[0]
     b = _lat(cfg)
     b.stats_reset()
