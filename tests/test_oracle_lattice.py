@@ -57,18 +57,21 @@ def test_hermite_projection_factor():
     With the factor printed in eq. f_i_neq (w_i/c_s^4) the second moment would
     be 2 Pi_neq; the test documents that reading.
     """
-    A = RNG.normal(size=(3, 3, 7))
+    rng = np.random.default_rng(77)   # own stream: the draws do not depend on which tests ran first
+    A = rng.normal(size=(3, 3, 7))
     pi = 0.5 * (A + A.transpose(1, 0, 2)) * 1e-3
     h = L.hermite_part(pi)
-    np.testing.assert_allclose(h.sum(0), 0.0, atol=1e-18)
-    np.testing.assert_allclose(np.einsum("ia,i...->a...", L.C.astype(float), h), 0.0, atol=1e-18)
+    # entries of h are ~1e-4; a 19-term FP64 sum of them rounds at ~1e-19 each,
+    # a wrong factor or sign would leave O(1e-4)
+    np.testing.assert_allclose(h.sum(0), 0.0, atol=1e-17)
+    np.testing.assert_allclose(np.einsum("ia,i...->a...", L.C.astype(float), h), 0.0, atol=1e-17)
     np.testing.assert_allclose(L.second_moment(h), pi, atol=1e-17)
     np.testing.assert_allclose(L.second_moment(2.0 * h), 2.0 * pi, atol=1e-17)
-    j = RNG.normal(size=(3, 7)) * 1e-3
+    j = rng.normal(size=(3, 7)) * 1e-3
     h1 = L.first_order_part(j)
     np.testing.assert_allclose(np.einsum("ia,i...->a...", L.C.astype(float), h1), j, atol=1e-17)
-    np.testing.assert_allclose(h1.sum(0), 0.0, atol=1e-18)
-    np.testing.assert_allclose(L.second_moment(h1), 0.0, atol=1e-18)
+    np.testing.assert_allclose(h1.sum(0), 0.0, atol=1e-17)
+    np.testing.assert_allclose(L.second_moment(h1), 0.0, atol=1e-17)
 
 
 @pytest.mark.parametrize("force", [(0.0, 0.0, 0.0), (2e-5, -1e-5, 3e-6)])
