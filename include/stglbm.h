@@ -158,7 +158,9 @@ int stglbm_stg_generate(stglbm_t h, int64_t t_step, float* d_u_plane);
 
 /* Advance n_steps time steps (Algorithm 1, steps 5-12): for each step the STG
  * plane at t+1 (one launch makes the planes of 16 consecutive steps, kept until
- * used, also by later calls), then one fused pass: pull streaming with
+ * used, also by later calls; while a 16-bit store samples statistics, each
+ * step launch then makes the plane two steps ahead in trailing blocks of its
+ * own, bit-identical to the STG launch's), then one fused pass: pull streaming with
  * bounce-back walls and spanwise wrap, regularized inlet rebuild (eqs. f_i ..
  * bc_eq) behind the guard |u_x| < 0.3 c_s, regularized pressure outlet,
  * moments, Smagorinsky tau_eff (eqs. strain, tau_eff), the sponge (eq.
@@ -266,9 +268,11 @@ int stglbm_restore(stglbm_t h, const void* h_buf, uint64_t n);
  * handle's stream.  enable = 0: off; enable = k >= 1: every STG launch and
  * every k-th step-kernel launch (the first after this call, then one in k),
  * so that the events' own cost (a few us per recorded launch) stays off most
- * steps.  out[5] = {timed step-kernel ms total, timed step launches, STG-kernel
- * ms total, inlet planes generated, STG launches}; reading synchronizes and
- * clears.  n >= 5.  E_INVAL if enable < 0. */
+ * steps.  out = {timed step-kernel ms total, timed step launches, STG-kernel
+ * ms total, inlet planes generated by STG launches, STG launches[, planes
+ * made by the trailing blocks of step launches (their time is part of the
+ * step kernel's)]}; reading synchronizes and clears.  n >= 5 (6 for the last
+ * value).  E_INVAL if enable < 0. */
 int stglbm_profile(stglbm_t h, int32_t enable);
 int stglbm_profile_read(stglbm_t h, double* out, uint64_t n);
 

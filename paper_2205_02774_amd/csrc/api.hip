@@ -56,6 +56,7 @@ struct Layout {
   bool short_chunks_when_idle = true;   // steps without statistics: their own shape
   int wx_idle = 1, nxg_idle = 1, lw_idle = 1;
   int remap_env = -1, lockstep = 1;   // tuning overrides read once per handle (-1: no override)
+  int tail_planes = 1;                // statistics launches may make the next inlet plane in trailing blocks
 };
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -120,6 +121,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   if (set_size(d) != 19 || d->collision != 0) vec = 1;   // the variants are built for one cell per lane
   if (const char* env = std::getenv("STGLBM_REMAP")) L.remap_env = std::atoi(env) ? 1 : 0;
   if (const char* env = std::getenv("STGLBM_LOCKSTEP")) L.lockstep = std::atoi(env) ? 1 : 0;
+  if (const char* env = std::getenv("STGLBM_TAIL_STG")) L.tail_planes = std::atoi(env) ? 1 : 0;
   L.vec = vec;
   L.nxt = (d->nx + 64 * vec - 1) / (64 * vec);
   const int wx_row = L.nxt < 8 ? L.nxt : 8;   // whole rows of up to 8 tiles
@@ -249,10 +251,12 @@ struct stglbm_ctx {
   int probe_xyz[kMaxProbes][3] = {};
   float* probe_out = nullptr;
   int64_t probe_capacity = 0, probe_rows = 0;
-  size_t n_step = 0, n_stg = 0, n_planes = 0;
-  // Inlet planes of the steps ring_t0 .. ring_t0 + ring_n - 1, made by one STG
-  // launch ahead of use (ring_n = 0: none valid).
-  int64_t ring_t0 = 0;
+  size_t n_step = 0, n_stg = 0, n_planes = 0, n_tail_planes = 0;
+  // Inlet planes of the steps ring_t0 .. ring_t0 + ring_n - 1 held in the
+  // ring of kStgBatch planes (step t in slot (t - ring_base) mod kStgBatch),
+  // made ahead of use by a plane-kernel launch or by the trailing blocks of a
+  // stream-collide launch (ring_n = 0: none valid).
+  int64_t ring_t0 = 0, ring_base = 0;
   int ring_n = 0;
 
   template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
@@ -356,9 +360,15 @@ StepParams step_params(stglbm_t h) {
   return p;
 }
 
-// STG planes of the n consecutive steps t_first .. t_first + n - 1, written
-// one after the other to out (n <= kStgBatch), in one launch.
-int launch_planes(stglbm_t h, int64_t t_first, int n, float* out, bool timed_ok = true) {
+// Ring slot of the inlet plane of step t.
+float* ring_slot(stglbm_t h, int64_t t) {
+  const int64_t k = ((t - h->ring_base) % kStgBatch + kStgBatch) % kStgBatch;
+  return h->at<float>(h->L.ubc) + static_cast<uint64_t>(k) * h->plane_floats();
+}
+
+// Plane parameters of the n consecutive steps t_first .. t_first + n - 1,
+// written one after the other to out.
+StgParams stg_params(stglbm_t h, int64_t t_first, int n, float* out) {
   StgParams s{};
   s.modes = h->at<double>(h->L.modes);
   s.arow = h->at<double2>(h->L.arow);
@@ -373,6 +383,13 @@ int launch_planes(stglbm_t h, int64_t t_first, int n, float* out, bool timed_ok 
   const double kTwoPi = 6.283185307179586476925;
   for (int b = 0; b < n; ++b)
     s.tphase[b] = kTwoPi * (0.0 - h->U_b * (static_cast<double>(t_first + b) * h->c_t)) / h->L_e;
+  return s;
+}
+
+// STG planes of the n consecutive steps t_first .. t_first + n - 1, written
+// one after the other to out (n <= kStgBatch), in one launch.
+int launch_planes(stglbm_t h, int64_t t_first, int n, float* out, bool timed_ok = true) {
+  const StgParams s = stg_params(h, t_first, n, out);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = timed_ok && h->prof;
   if (timed) {
@@ -395,20 +412,32 @@ int ring_plane(stglbm_t h, int64_t t, const float** plane) {
   if (h->ring_n == 0 || t < h->ring_t0 || t >= h->ring_t0 + h->ring_n) {
     h->ring_n = 0;
     if (int rc = launch_planes(h, t, kStgBatch, h->at<float>(h->L.ubc))) return rc;
-    h->ring_t0 = t;
+    h->ring_t0 = h->ring_base = t;
     h->ring_n = kStgBatch;
   }
-  *plane = h->at<float>(h->L.ubc) + static_cast<uint64_t>(t - h->ring_t0) * h->plane_floats();
+  *plane = ring_slot(h, t);
   return STGLBM_OK;
 }
 
 // One time step: the fused stream-collide launch reading the inlet plane
 // `plane` (null for periodic x), the buffer swap and the probes.  With
 // `timed`, the profiler's events may bracket the launch (they are created on
-// first use, so the allocation-free entry point passes false).
-int step_once(stglbm_t h, const float* plane, bool timed_ok) {
+// first use, so the allocation-free entry point passes false).  With
+// `ring_ahead`, a statistics launch without a body force also makes the plane
+// of step t + 2 in its trailing blocks when the ring holds planes up to t + 1
+// (ring steps need blocks of at least kStgWaves waves).
+int step_once(stglbm_t h, const float* plane, bool timed_ok, bool ring_ahead = false) {
   StepParams p = step_params(h);
   p.ubc = plane;
+  const int64_t t2 = h->t + 2;
+  const bool tail = ring_ahead && h->L.tail_planes && plane && h->sampling && !p.has_force &&
+                    h->d.store != STGLBM_F32 && p.wx * p.wz >= kStgWaves &&
+                    h->ring_n > 0 && h->ring_t0 + h->ring_n == t2 && h->ring_t0 <= h->t + 1;
+  if (tail) {
+    p.stg_zb = (h->d.nz + 63) / 64;
+    p.stg_blocks = p.stg_zb * ((h->d.ny + kStgTailRows - 1) / kStgTailRows);
+    p.stg = stg_params(h, t2, 1, ring_slot(h, t2));
+  }
   const bool window = h->sampling && h->d.store != STGLBM_F32;
   if (window) p.win_first = h->n_samples % kStatsWindow == 0 ? 1 : 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -422,6 +451,13 @@ int step_once(stglbm_t h, const float* plane, bool timed_ok) {
   if (timed && e0 && e1) {
     HIP_CHECK(h, hipEventRecord(e1, h->stream), "hipEventRecord");
     ++h->n_step;
+  }
+  if (tail) {
+    // plane t + 2 replaces the one kStgBatch steps earlier in its slot
+    const int64_t end = t2 + 1;
+    h->ring_t0 = std::max(h->ring_t0, end - kStgBatch);
+    h->ring_n = static_cast<int>(end - h->ring_t0);
+    ++h->n_tail_planes;
   }
   h->cur = 1 - h->cur;
   ++h->t;
@@ -632,7 +668,7 @@ int stglbm_step(stglbm_t h, int32_t n_steps) {
     if (!h->d.periodic_x) {
       if (int rc = ring_plane(h, h->t + 1, &plane)) return rc;
     }
-    if (int rc = step_once(h, plane, true)) return rc;
+    if (int rc = step_once(h, plane, true, true)) return rc;
   }
   return STGLBM_OK;
 }
@@ -981,7 +1017,8 @@ int stglbm_profile_read(stglbm_t h, double* out, uint64_t n) {
   }
   out[0] = ms_step; out[1] = static_cast<double>(h->n_step);
   out[2] = ms_stg; out[3] = static_cast<double>(h->n_planes); out[4] = static_cast<double>(h->n_stg);
-  h->n_step = h->n_stg = h->n_planes = 0;
+  if (n >= 6) out[5] = static_cast<double>(h->n_tail_planes);
+  h->n_step = h->n_stg = h->n_planes = h->n_tail_planes = 0;
   return STGLBM_OK;
 }
 

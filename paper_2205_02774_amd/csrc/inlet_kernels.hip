@@ -23,6 +23,7 @@
 #include <cstdlib>
 
 #include "stglbm_internal.h"
+#include "stg_block.h"
 
 namespace stglbm {
 namespace {
@@ -233,126 +234,17 @@ __global__ void inlet_zphase_kernel(SetupParams p) {
     p.sig[m] = make_float4(static_cast<float>(md[4]), static_cast<float>(md[5]), static_cast<float>(md[6]), 0.0f);
 }
 
-// Inlet plane: v' = sqrt 6 sum_n sqrt(q^n) sigma^n cos(psi_n) (eq. aux_vec),
-// u' = a v' (eq. v_fluc), u_bc = (U + u') c_t / c_x (eqs. u_phys, u_transfer).
-// The phase splits into a row part (FP64 per row, mode and step, kept as the
-// FP32 phasor P = sqrt 6 sqrt(q) exp(i psi_row)) and the spanwise phasor
-// B = exp(i k d_z z) of the precomputed table, so cos(psi) = Re(P B) / |P|.
-// Block: kStgRows rows x 64 spanwise nodes of one plane; wave w sums the
-// modes n = w mod 8 for all the block's rows, so each B loaded from the table
-// serves kStgRows rows; the 8 partial sums meet in LDS in a fixed order.  One
-// launch writes n_planes consecutive steps (grid z); kStgRows is chosen so
-// that the grid still has >= 2048 waves.  The inlet guard |u_x| < 0.3 c_s is
-// applied where a plane is used, by the step kernel.
+// Inlet planes of n_planes consecutive steps (grid z), kStgRows rows x 64
+// spanwise nodes per block (stg_block.h); kStgRows is chosen so that the grid
+// still has >= 2048 waves.  The inlet guard |u_x| < 0.3 c_s is applied where a
+// plane is used, by the step kernel.
 template <int kStgRows>
 __global__ __launch_bounds__(64 * kStgWaves) void stg_plane_kernel(StgParams p) {
-  const int lane = threadIdx.x;
-  const int w = threadIdx.y;
-  const int tid = w * 64 + lane;
-  const int j0 = blockIdx.y * kStgRows;
-  const int z = blockIdx.x * 64 + lane;
-  const double tphase = p.tphase[blockIdx.z];
-  const int zc = z < p.nz ? z : p.nz - 1;
-  // Modes staged per pass; the row phasors and sigma of the last pass are dead
-  // when the partial sums meet, so the two share LDS (under 64 KiB per block).
+  // modes staged per pass: the row phasors and sigma of the last pass are
+  // dead when the partial sums meet, so the two share LDS (under 64 KiB)
   constexpr int kChunk = kStgChunk * 2 / (kStgRows >= 2 ? kStgRows : 2);
-  constexpr int kStageBytes = kStgRows * kChunk * 8 + kChunk * 16 + kChunk * 16;
-  constexpr int kRedBytes = kStgWaves * 3 * kStgRows * 64 * 4;
-  __shared__ __attribute__((aligned(16))) char smem[kStageBytes > kRedBytes ? kStageBytes : kRedBytes];
-  float2 (*P)[kChunk] = reinterpret_cast<float2 (*)[kChunk]>(smem);
-  float4* SG = reinterpret_cast<float4*>(smem + kStgRows * kChunk * 8);
-  double2* G = reinterpret_cast<double2*>(smem + kStgRows * kChunk * 8 + kChunk * 16);
-  float (*red)[3 * kStgRows][64] = reinterpret_cast<float (*)[3 * kStgRows][64]>(smem);
-  float v[kStgRows][3];
-#pragma unroll
-  for (int r = 0; r < kStgRows; ++r) v[r][0] = v[r][1] = v[r][2] = 0.f;
-  for (int base = 0; base < p.n_modes; base += kChunk) {
-    const int cnt = min(kChunk, p.n_modes - base);
-    // time part of the phase, per mode: exp(i 2 pi d_x (x_in - U_b t) / L_e)
-    for (int m = tid; m < cnt; m += 64 * kStgWaves) {
-      double sn, cs;
-      sincos(p.modes[(long long)(base + m) * kModeFields + 1] * tphase, &sn, &cs);
-      G[m] = make_double2(cs, sn);
-      SG[m] = p.sig[base + m];
-    }
-    __syncthreads();
-    // P = sqrt 6 sqrt(q) exp(i psi_row) of the full row part: the stored
-    // time-independent phasor times the time part, in FP64, rounded once
-    for (int e = tid; e < kStgRows * cnt; e += 64 * kStgWaves) {
-      const int r = e / cnt, m = e - r * cnt;
-      const int j = j0 + r;
-      float2 ph = make_float2(0.f, 0.f);
-      if (j < p.ny) {
-        const double2 a = p.arow[(long long)j * p.n_modes + base + m];
-        const double2 g = G[m];
-        ph = make_float2(static_cast<float>(a.x * g.x - a.y * g.y), static_cast<float>(a.x * g.y + a.y * g.x));
-      }
-      P[r][m] = ph;
-    }
-    __syncthreads();
-    const float2* bz = p.bz + (long long)base * p.nz + zc;
-    const long long step = (long long)kStgWaves * p.nz;
-    int m = w;
-    constexpr int kInFlight = 8;   // phasor loads in flight per wave
-    for (; m + (kInFlight - 1) * kStgWaves < cnt; m += kInFlight * kStgWaves) {
-      float2 Bs[kInFlight];
-#pragma unroll
-      for (int u = 0; u < kInFlight; ++u) Bs[u] = bz[(long long)m * p.nz + u * step];
-#pragma unroll
-      for (int u = 0; u < kInFlight; ++u) {
-        const float4 S = SG[m + u * kStgWaves];
-#pragma unroll
-        for (int r = 0; r < kStgRows; ++r) {
-          const float2 Pm = P[r][m + u * kStgWaves];
-          const float c = Pm.x * Bs[u].x - Pm.y * Bs[u].y;   // scaled cos of the full phase
-          v[r][0] += S.x * c;
-          v[r][1] += S.y * c;
-          v[r][2] += S.z * c;
-        }
-      }
-    }
-    for (; m < cnt; m += kStgWaves) {
-      const float2 B = bz[(long long)m * p.nz];
-      const float4 S = SG[m];
-#pragma unroll
-      for (int r = 0; r < kStgRows; ++r) {
-        const float2 Pm = P[r][m];
-        const float c = Pm.x * B.x - Pm.y * B.y;
-        v[r][0] += S.x * c;
-        v[r][1] += S.y * c;
-        v[r][2] += S.z * c;
-      }
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int r = 0; r < kStgRows; ++r)
-#pragma unroll
-    for (int c = 0; c < 3; ++c) red[w][3 * r + c][lane] = v[r][c];
-  __syncthreads();
-  // one thread per (row, node) of the block: waves 0 .. kStgRows-1 take one row each
-  if (w < kStgRows) {
-    const int j = j0 + w;
-    if (j < p.ny && z < p.nz) {
-      float vs[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        float acc = red[0][3 * w + c][lane];
-#pragma unroll
-        for (int k = 1; k < kStgWaves; ++k) acc += red[k][3 * w + c][lane];
-        vs[c] = acc;
-      }
-      const double* row = p.rows + (long long)j * kRowFields;
-      const double a11 = row[11], a21 = row[12], a22 = row[13], a31 = row[14], a32 = row[15], a33 = row[16];
-      const double u0 = row[0] + a11 * vs[0];
-      const double u1 = row[1] + a21 * vs[0] + a22 * vs[1];
-      const double u2 = row[2] + a31 * vs[0] + a32 * vs[1] + a33 * vs[2];
-      float* o = p.out + 3 * ((long long)blockIdx.z * p.ny * p.nz + (long long)j * p.nz + z);
-      o[0] = static_cast<float>(u0 * p.conv);
-      o[1] = static_cast<float>(u1 * p.conv);
-      o[2] = static_cast<float>(u2 * p.conv);
-    }
-  }
+  __shared__ __attribute__((aligned(16))) char smem[stg_block_lds<kStgRows, kChunk>()];
+  stg_plane_block<kStgRows, kChunk, 8>(p, blockIdx.z, blockIdx.x, blockIdx.y, threadIdx.x, threadIdx.y, smem);
 }
 
 }  // namespace

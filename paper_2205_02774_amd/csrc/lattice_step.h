@@ -14,6 +14,7 @@
 // Included by the translation units that instantiate it; everything here has
 // internal linkage.
 #pragma once
+#include "stg_block.h"
 #include "stglbm_internal.h"
 
 #include <type_traits>
@@ -254,10 +255,30 @@ __device__ __forceinline__ unsigned from_next_lane(unsigned v) {
 // along x: the element that crosses a lane boundary comes from the
 // neighbouring lane by a DPP shift, and only the first and last lanes of a
 // wave load it from memory.
+//
+// In 16-bit statistics launches without a body force, blocks past the
+// lattice's (blockIdx.x >= p.nblocks) make part of the inlet plane of a later
+// step (stg_block.h, kStgTailRows rows x 64 spanwise nodes each).  They are
+// dispatched after every lattice block and take slots as the last round of
+// lattice blocks drains.  FP32 statistics launches run one round of 16-wave
+// blocks, one per compute unit: there the plane blocks would run past the
+// last lattice block, so those launches leave the path out, and so do the
+// other instantiations (it would raise their registers and cost occupancy).
+template <bool kPath, int SB>
+constexpr bool kStgTail = kPath && SB == 2;
+
 template <class Codec, int QN, bool REG, int V, bool STATS, bool FORCE>
 __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage), QN, V, STATS)) void step_kernel(StepParams p) {
   using S = typename Codec::storage;
   constexpr int SB = static_cast<int>(sizeof(S));
+  if (kStgTail<STATS && !FORCE, SB> && blockIdx.x >= p.nblocks) {
+    extern __shared__ __attribute__((aligned(16))) char stg_smem[];
+    const int item = blockIdx.x - p.nblocks;
+    const int w = (threadIdx.x >> 6) + (blockDim.x >> 6) * threadIdx.y;
+    stg_plane_block<kStgTailRows, kStgTailChunk, kStgTailInFlight>(p.stg, 0, item % p.stg_zb, item / p.stg_zb,
+                                                                   threadIdx.x & 63, w, stg_smem);
+    return;
+  }
   using Vec = Raw<V * SB>;
   using One = Raw<SB>;
   constexpr int NW = Vec::kWords;
@@ -697,14 +718,19 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
 template <class Codec, int QN, bool REG, int V>
 hipError_t launch_step_v(const StepParams& p, bool stats, hipStream_t s) {
   const dim3 block(64 * p.wx, p.wz);
-  const dim3 grid(p.nblocks);
-  const size_t lds = (stats && p.wz > 1) ? sizeof(float) * 9 * 64 * V * p.wx * p.wz : 0;
+  // trailing plane blocks: 16-bit statistics launches without a force, kStgWaves waves per block
+  if (p.stg_blocks > 0 && (!stats || p.has_force || sizeof(typename Codec::storage) != 2 || p.wx * p.wz < kStgWaves))
+    return hipErrorInvalidValue;
+  const dim3 grid(p.nblocks + p.stg_blocks);
+  size_t lds = (stats && p.wz > 1) ? sizeof(float) * 9 * 64 * V * p.wx * p.wz : 0;
+  constexpr size_t kStgLds = stg_block_lds<kStgTailRows, kStgTailChunk>();
+  if (p.stg_blocks > 0 && lds < kStgLds) lds = kStgLds;
   if (p.has_force) {
     if (stats) step_kernel<Codec, QN, REG, V, true, true><<<grid, block, lds, s>>>(p);
-    else step_kernel<Codec, QN, REG, V, false, true><<<grid, block, 0, s>>>(p);
+    else step_kernel<Codec, QN, REG, V, false, true><<<grid, block, lds, s>>>(p);
   } else {
     if (stats) step_kernel<Codec, QN, REG, V, true, false><<<grid, block, lds, s>>>(p);
-    else step_kernel<Codec, QN, REG, V, false, false><<<grid, block, 0, s>>>(p);
+    else step_kernel<Codec, QN, REG, V, false, false><<<grid, block, lds, s>>>(p);
   }
   return hipGetLastError();
 }

@@ -13,7 +13,10 @@ constexpr int kMaxWavesPerBlock = 8; // step kernel: waves along x times waves a
 constexpr int kMaxWavesWide = 16;    // FP32 statistics launches of D3Q15 / D3Q19, one cell per lane
 constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel (2048 / rows for 4 and 8 rows)
 constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
-constexpr int kStgBatch = 16;       // inlet planes generated per STG launch during stepping
+constexpr int kStgBatch = 16;       // inlet planes per plane-kernel launch; ring of planes made ahead
+constexpr int kStgTailRows = 2;     // rows per plane block of a 16-bit statistics launch
+constexpr int kStgTailInFlight = 2; // spanwise phasor loads in flight per wave there (at most 80 VGPRs)
+constexpr int kStgTailChunk = 256;  // modes staged per pass there (12 KiB of LDS)
 
 // Waves per block a step-kernel instantiation is built for.  The FP32
 // statistics launches of D3Q15 and D3Q19 with one cell per lane fit 16 waves
@@ -27,6 +30,22 @@ constexpr int step_max_waves(int store_bytes, int q, int vec, bool stats) {
 // Flag bits written by the kernels into the handle's status word.
 constexpr int kFlagDensity = 1;     // |rho - 1| >= 0.5 or NaN in the step kernel
 constexpr int kFlagInletMach = 2;   // |u_bc,x| >= 0.3 c_s at an inlet node
+
+// STG inlet planes: a launch of the plane kernel, or the trailing blocks of a
+// stream-collide launch.
+struct StgParams {
+  const double* modes;      // [N][8]
+  const double2* arow;      // [NY][N] sqrt 6 sqrt(q^n) exp(i (k^n d^n_y y_j + phi^n))
+  const float2* bz;         // [N][NZ] spanwise phasors exp(i k d_z z)
+  const float4* sig;        // [N] sigma^n in FP32 (x, y, z, 0)
+  const double* rows;       // [NY][18]
+  float* out;               // n_planes planes [NY][NZ][3], one after the other
+  int ny, nz, n_modes;
+  int n_planes;             // 1 .. kStgBatch consecutive steps
+  double c_x;               // lattice spacing (m)
+  double conv;              // c_t / c_x
+  double tphase[kStgBatch]; // 2 pi (x_in - U_b t) / L_e for the step of each plane
+};
 
 // Fused stream-collide pass, one launch per time step.
 struct StepParams {
@@ -61,6 +80,11 @@ struct StepParams {
   float* win;               // 16-bit stores: [slots][9][NY][NX] FP32 sums of the current window
   int win_first;            // 16-bit stores: first sampled step of a window (store, not add)
   int* flag;
+  // Trailing blocks (blockIdx.x >= nblocks) make one inlet plane of a later
+  // step while the launch's last lattice blocks finish (0: none).
+  int stg_blocks;
+  int stg_zb;               // blocks of 64 spanwise nodes per plane row group
+  StgParams stg;            // that plane: out, tphase[0]
 };
 
 // Statistics of 16-bit stores: every launch adds its per-slot sums to FP32
@@ -77,21 +101,6 @@ struct ProbeParams {
   double fx, fy, fz;        // Guo acceleration (u = (sum c f - F/2) / rho)
   int xyz[kMaxProbes][3];
   float* out;               // this step's row of the series: [n][3]
-};
-
-// STG inlet plane, one launch per time step.
-struct StgParams {
-  const double* modes;      // [N][8]
-  const double2* arow;      // [NY][N] sqrt 6 sqrt(q^n) exp(i (k^n d^n_y y_j + phi^n))
-  const float2* bz;         // [N][NZ] spanwise phasors exp(i k d_z z)
-  const float4* sig;        // [N] sigma^n in FP32 (x, y, z, 0)
-  const double* rows;       // [NY][18]
-  float* out;               // n_planes planes [NY][NZ][3], one after the other
-  int ny, nz, n_modes;
-  int n_planes;             // 1 .. kStgBatch consecutive steps
-  double c_x;               // lattice spacing (m)
-  double conv;              // c_t / c_x
-  double tphase[kStgBatch]; // 2 pi (x_in - U_b t) / L_e for the step of each plane
 };
 
 // One-off inlet precompute.

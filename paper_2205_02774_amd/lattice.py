@@ -265,11 +265,12 @@ class Lattice:
         self._chk(self.lib.stglbm_profile(self.handle, int(every) if enable else 0))
 
     def profile_read(self):
-        """{'step_ms', 'step_launches', 'stg_ms', 'stg_planes', 'stg_launches'} since the last read."""
-        out = np.zeros(5)
-        self._chk(self.lib.stglbm_profile_read(self.handle, _dptr(out), 5))
+        """{'step_ms', 'step_launches', 'stg_ms', 'stg_planes', 'stg_launches', 'tail_planes'} since the last
+        read (tail_planes: planes made by the trailing blocks of step launches)."""
+        out = np.zeros(6)
+        self._chk(self.lib.stglbm_profile_read(self.handle, _dptr(out), 6))
         return {"step_ms": out[0], "step_launches": int(out[1]), "stg_ms": out[2], "stg_planes": int(out[3]),
-                "stg_launches": int(out[4])}
+                "stg_launches": int(out[4]), "tail_planes": int(out[5])}
 
 
 def channel_from_config(cfg, *, store=None, device="cuda", stream=None, periodic_x=False, max_modes=None,

@@ -77,3 +77,43 @@ def test_restore_then_step_reproduces():
     lat.step(4)
     np.testing.assert_array_equal(lat.get_f(), ref)
     lat.close()
+
+
+@pytest.mark.parametrize("store", ["f16", "bf16", "f32"])
+def test_planes_from_trailing_blocks(store, monkeypatch):
+    """16-bit statistics launches of rows of 512 cells (8-wave blocks) make
+    the inlet plane of step t + 2 in trailing blocks once the ring's first
+    batch is used up (from the 15th step on); FP32 launches never do.  Those
+    planes are bit-identical to the plane kernel's (same mode order and the
+    same explicit multiply/FMA chain per node), so f and the statistics match
+    a run with the trailing blocks switched off (tuning override
+    STGLBM_TAIL_STG=0) bit for bit over 40 steps, across calls of different
+    lengths and a statistics restart.  (The plane kernel's planes are checked
+    against the oracle's STG in the inlet tests.)"""
+    from paper_2205_02774_amd import channel_from_config
+    cfg = small_channel(512, 8, 70, n_modes=37, seed=9)
+    runs = {}
+    for tail in ("1", "0"):
+        monkeypatch.setenv("STGLBM_TAIL_STG", tail)
+        print(f"[gpu] trailing plane blocks {tail} {store} {cfg['name']}", flush=True)
+        lat = channel_from_config(cfg, store=store, device="cuda:0")
+        lat.stats_reset()
+        lat.profile(True)
+        lat.step(13)
+        lat.step(1)
+        lat.step(11)
+        lat.stats_reset()
+        lat.step(15)
+        prof = lat.profile_read()
+        st, n = lat.get_stats()
+        runs[tail] = (lat.get_f(), st, n, prof)
+        lat.close()
+    f1, st1, n1, prof1 = runs["1"]
+    f0, st0, n0, prof0 = runs["0"]
+    print(f"[gpu] planes: trailing blocks {prof1['tail_planes']} + plane kernel {prof1['stg_planes']}; "
+          f"switched off {prof0['tail_planes']} + {prof0['stg_planes']}", flush=True)
+    assert prof0["tail_planes"] == 0
+    assert prof1["tail_planes"] > 20 if store != "f32" else prof1["tail_planes"] == 0
+    assert n1 == n0 == 15
+    np.testing.assert_array_equal(f1, f0)
+    np.testing.assert_array_equal(st1, st0)
