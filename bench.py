@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0                       # MI355X HBM3E
 PROFILE_EVERY = 8
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2205_02774_amd", "csrc", f)
-               for f in ("lattice_step.h", "stg_block.h", "lattice_kernels.hip")]
+               for f in ("lattice_step.h", "stg_block.h", "stglbm_internal.h", "lattice_kernels.hip")]
 
 
 def log(msg):
@@ -51,7 +51,8 @@ def code_text(source):
 
 
 def kernel_hash():
-    """Hash of the code of the stream-collide kernel (its header and the unit that instantiates it).
+    """Hash of the code of the stream-collide kernel (the unit that instantiates it and every
+    header of the library that unit includes).
 
     Comments are dropped and white space collapsed first, so that a change of
     wording alone keeps the counter record of an unchanged kernel valid.
@@ -81,6 +82,10 @@ def run_variant(cfg, store, steps, warmup, stats=True, velocity_set=19, collisio
     t0 = time.perf_counter()
     lat = channel_from_config(cfg, store=store, device="cuda:0", velocity_set=velocity_set, collision=collision)
     try:
+        if stats:
+            # warm up the launch that is timed (statistics on; the sums are cleared below), so
+            # that the inlet planes are made as in a long statistics run when timing starts
+            lat.stats_reset()
         lat.step(warmup)
         lat.sync()
     except Exception:

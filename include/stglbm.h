@@ -271,8 +271,8 @@ int stglbm_restore(stglbm_t h, const void* h_buf, uint64_t n);
  * steps.  out = {timed step-kernel ms total, timed step launches, STG-kernel
  * ms total, inlet planes generated by STG launches, STG launches[, planes
  * made by the trailing blocks of step launches (their time is part of the
- * step kernel's)]}; reading synchronizes and clears.  n >= 5 (6 for the last
- * value).  E_INVAL if enable < 0. */
+ * step kernel's)]}, all counted while profiling is on; reading synchronizes
+ * and clears.  n >= 5 (6 for the last value).  E_INVAL if enable < 0. */
 int stglbm_profile(stglbm_t h, int32_t enable);
 int stglbm_profile_read(stglbm_t h, double* out, uint64_t n);
 

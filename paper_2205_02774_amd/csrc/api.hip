@@ -457,7 +457,7 @@ int step_once(stglbm_t h, const float* plane, bool timed_ok, bool ring_ahead = f
     const int64_t end = t2 + 1;
     h->ring_t0 = std::max(h->ring_t0, end - kStgBatch);
     h->ring_n = static_cast<int>(end - h->ring_t0);
-    ++h->n_tail_planes;
+    if (h->prof) ++h->n_tail_planes;   // counted like the other profile figures, while profiling
   }
   h->cur = 1 - h->cur;
   ++h->t;

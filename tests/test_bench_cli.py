@@ -16,9 +16,21 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_kernel_hash_covers_the_stream_collide_sources():
+    """The hash covers the unit that instantiates the step kernel and every
+    library header it includes, directly or not."""
+    import re
     sys.path.insert(0, ROOT)
     import bench
-    assert {os.path.basename(p) for p in bench.KERNEL_SRCS} == {"lattice_step.h", "lattice_kernels.hip"}
+    csrc = os.path.join(ROOT, "paper_2205_02774_amd", "csrc")
+    seen, todo = set(), ["lattice_kernels.hip"]
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(os.path.join(csrc, f)):
+            continue
+        seen.add(f)
+        todo += re.findall(r'#include "([^"]+)"', open(os.path.join(csrc, f)).read())
+    assert "stg_block.h" in seen and "lattice_step.h" in seen
+    assert {os.path.basename(p) for p in bench.KERNEL_SRCS} == seen
     h = bench.kernel_hash()
     assert len(h) == 16 and h == bench.kernel_hash()
 
