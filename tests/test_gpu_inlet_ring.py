@@ -79,8 +79,10 @@ def test_restore_then_step_reproduces():
     lat.close()
 
 
-@pytest.mark.parametrize("store", ["f16", "bf16", "f32"])
-def test_planes_from_trailing_blocks(store, monkeypatch):
+@pytest.mark.parametrize("store,shape", [("f16", (512, 8, 70, 37)), ("bf16", (512, 8, 70, 37)),
+                                         ("f32", (512, 8, 70, 37)), ("f16", (520, 7, 33, 3)),
+                                         ("f16", (512, 5, 64, 300))])
+def test_planes_from_trailing_blocks(store, shape, monkeypatch):
     """16-bit statistics launches of rows of 512 cells (8-wave blocks) make
     the inlet plane of step t + 2 in trailing blocks once the ring's first
     batch is used up (from the 15th step on); FP32 launches never do.  Those
@@ -88,10 +90,14 @@ def test_planes_from_trailing_blocks(store, monkeypatch):
     same explicit multiply/FMA chain per node), so f and the statistics match
     a run with the trailing blocks switched off (tuning override
     STGLBM_TAIL_STG=0) bit for bit over 40 steps, across calls of different
-    lengths and a statistics restart.  (The plane kernel's planes are checked
-    against the oracle's STG in the inlet tests.)"""
+    lengths and a statistics restart.  Shapes: a ragged spanwise block (NZ =
+    70 and 33), an odd NY (the last row pair half empty), fewer modes than
+    waves (3: five waves sum nothing) and more modes than one staging pass
+    holds (300 > 256).  (The plane kernel's planes are checked against the
+    oracle's STG in the inlet tests.)"""
     from paper_2205_02774_amd import channel_from_config
-    cfg = small_channel(512, 8, 70, n_modes=37, seed=9)
+    nx, ny, nz, modes = shape
+    cfg = small_channel(nx, ny, nz, n_modes=modes, seed=9)
     runs = {}
     for tail in ("1", "0"):
         monkeypatch.setenv("STGLBM_TAIL_STG", tail)
