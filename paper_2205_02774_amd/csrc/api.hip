@@ -56,6 +56,8 @@ struct Layout {
   bool short_chunks_when_idle = true;   // steps without statistics: their own shape
   int wx_idle = 1, nxg_idle = 1, lw_idle = 1;
   int remap_env = -1, lockstep = 1;   // tuning overrides read once per handle (-1: no override)
+  int zsched = 0;                     // statistics launches: unequal z chunks, slot s on rows zbeg[s] .. zbeg[s + 1] - 1
+  int zbeg[kMaxZChunks + 1] = {};
   int tail_planes = 1;                // statistics launches may make the next inlet plane in trailing blocks
 };
 
@@ -91,6 +93,41 @@ const char* check_desc(const stglbm_lattice_desc* d) {
   for (int a = 0; a < 3; ++a)
     if (!std::isfinite(d->force[a])) return "force must be finite";
   return nullptr;
+}
+
+// Statistics launches of 16-bit stores in whole-row blocks of 8 waves: MI355X
+// holds 3 such blocks per compute unit (the kernel stays at <= 80 VGPRs), 768
+// on its 256 CUs.  When that is a whole number spr >= 3 of slots (blocks per
+// slot = base, the x groups times NY), the z rows are cut into 2 spr chunks
+// that fill exactly two rounds of resident blocks: spr long chunks first,
+// spr - 2 slightly shorter ones, then 2 short ones, which go to the positions
+// that free up last.  The short chunks are about half a mean chunk; fewer
+// slots than the uniform rule's (12 against 16 on 512x128x256) mean fewer
+// window-sum bytes per launch.  Measured on 512x128x256 FP16 (ms per step,
+// one box): 24 x 6, 22 x 4, 12 x 2 rows 0.2575 against 0.2633 for 16 chunks
+// of 16; neighbours of that schedule 0.2578-0.2586; 11 chunks (a round of 5
+// slots) 0.272.  Returns false (uniform chunks) where the rule does not apply.
+bool make_two_round_schedule(const stglbm_lattice_desc* d, Layout& L, int base) {
+  constexpr int kResident = 3 * 256;
+  if (d->store == STGLBM_F32 || L.wz != 1 || L.wx * L.wz != 8 || base <= 0 || kResident % base != 0) return false;
+  const int spr = kResident / base, n = 2 * spr, nz = d->nz;
+  if (spr < 3 || n > kMaxZChunks || nz < 4 * (n - 1)) return false;
+  const int small = (nz + (n - 1)) / (2 * (n - 1));                 // about half of nz / (n - 1)
+  const int rest = nz - 2 * small;
+  const int c1 = (rest + (n - 2) - 1) / (n - 2);                    // first round, rounded up
+  const int r2 = rest - spr * c1;                                   // rows left for the spr - 2 middle chunks
+  if (r2 < (spr - 2) * small) return false;
+  int chunk[kMaxZChunks];
+  for (int i = 0; i < spr; ++i) chunk[i] = c1;
+  for (int i = 0; i < spr - 2; ++i) chunk[spr + i] = r2 / (spr - 2) + (i < r2 % (spr - 2) ? 1 : 0);
+  chunk[n - 2] = chunk[n - 1] = small;
+  L.zbeg[0] = 0;
+  for (int i = 0; i < n; ++i) L.zbeg[i + 1] = L.zbeg[i] + chunk[i];
+  if (L.zbeg[n] != nz) return false;
+  L.zsched = 1;
+  L.slots = n;
+  L.lw = c1;
+  return true;
 }
 
 Layout make_layout(const stglbm_lattice_desc* d) {
@@ -131,6 +168,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   L.wz = wz;
   L.nxg = (L.nxt + wx - 1) / wx;
   const int base = L.nxg * d->ny;
+  const bool lw_default = lw == 0;
   if (lw == 0) {
     // Each block takes one contiguous z chunk; the blocks sharing an (x, y)
     // bin are its FP64 slots.  FP32 on D3Q15 / D3Q19 with one cell per lane:
@@ -138,7 +176,8 @@ Layout make_layout(const stglbm_lattice_desc* d) {
     // wave slots, so all its waves run in step and finish together), 2 slots,
     // more where the grid would hold fewer than 4096 waves.  Other FP32 sets:
     // one z wave, 4 slots.  16-bit stores: one z wave and as many slots as
-    // make 16384 waves.  Measured on MI355X, 512x128x256: FP32 0.455 ms (two
+    // make 16384 waves, unless the two-round schedule applies (see
+    // make_two_round_schedule).  Measured on MI355X, 512x128x256: FP32 0.455 ms (two
     // z waves and 4 slots 0.457; one z wave: 4 slots 0.476, 8: 0.482, 16: 0.494;
     // half rows with four z waves 0.477-0.479); with one z wave the two
     // 8-wave blocks sharing a CU ran at different speeds, and the first to
@@ -158,6 +197,30 @@ Layout make_layout(const stglbm_lattice_desc* d) {
     lw = (d->nz + wz * slots - 1) / (wz * slots);
   }
   L.lw = lw;
+  L.slots = (d->nz + wz * lw - 1) / (wz * lw);
+  const char* zenv = std::getenv("STGLBM_ZCHUNKS");   // "r0,r1,...": z rows per chunk, or "uniform" (tuning override)
+  if (!zenv) {
+    if (lw_default) make_two_round_schedule(d, L, base);
+  } else if (std::strcmp(zenv, "uniform") != 0) {
+    int beg[kMaxZChunks + 1] = {0}, n = 0, maxc = 0;
+    bool ok = true;
+    for (const char* c = zenv; *c && ok;) {
+      char* end = nullptr;
+      const long r = std::strtol(c, &end, 10);
+      if (end == c || r <= 0 || r % wz != 0 || n >= kMaxZChunks) { ok = false; break; }
+      beg[n + 1] = beg[n] + static_cast<int>(r);
+      maxc = std::max(maxc, static_cast<int>(r));
+      ++n;
+      c = *end == ',' ? end + 1 : end;
+    }
+    if (ok && n > 0 && beg[n] == d->nz) {
+      L.zsched = 1;
+      std::copy(beg, beg + n + 1, L.zbeg);
+      L.slots = n;
+      L.lw = maxc / wz;
+      interleave = 0;
+    }
+  }
   // Without statistics the z chunk only sets the block size.  Measured on
   // MI355X, the fastest blocks stream about 2 KB of each population row for
   // FP32 (one z row of 512 cells: 0.477 ms; two: 0.481) and about 4 KB for
@@ -167,7 +230,6 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   const int target = d->store == STGLBM_F32 ? 2048 : 4096;
   L.lw_idle = std::max(1, (target + block_row_bytes - 1) / block_row_bytes);
   L.nxg_idle = (L.nxt + L.wx_idle - 1) / L.wx_idle;
-  L.slots = (d->nz + wz * lw - 1) / (wz * lw);
   L.zstep = interleave ? L.slots * wz : wz;
   L.nblocks = base * L.slots;
   uint64_t off = 0;
@@ -318,7 +380,11 @@ StepParams step_params(stglbm_t h) {
   p.vec = h->L.vec;
   p.nxt = h->L.nxt; p.wx = h->L.wx; p.wz = h->L.wz; p.nxg = h->L.nxg;
   p.slots = h->L.slots; p.lw = h->L.lw; p.zstep = h->L.zstep; p.nblocks = h->L.nblocks;
-  if (!h->sampling && h->L.short_chunks_when_idle) {
+  if (h->sampling && h->L.zsched) {
+    p.zsched = 1;
+    std::copy(h->L.zbeg, h->L.zbeg + h->L.slots + 1, p.zbeg);
+  }
+  if (!h->sampling && (h->L.short_chunks_when_idle || h->L.zsched)) {
     // The block shape and z chunk serve the statistics reduction (they set the
     // number of FP64 slots).  Without statistics, whole-row blocks with short
     // chunks stream fastest: the resident blocks then cover a narrow

@@ -350,7 +350,13 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
   // zstep = slots * wz interleaves the blocks of one (x group, y) over z, so
   // the blocks resident at a time cover one contiguous band of z per
   // population plane; zstep = wz gives each block a contiguous z chunk.
-  const int z0 = slot * p.wz * (p.zstep == p.wz ? p.lw : 1) + wz;
+  int z0 = slot * p.wz * (p.zstep == p.wz ? p.lw : 1) + wz;
+  int trips = p.lw;
+  if (STATS && p.zsched) {
+    const int zb = p.zbeg[slot], ze = p.zbeg[slot + 1];
+    z0 = zb + wz;
+    trips = (ze - zb) / p.wz;
+  }
   // Statistics launches may keep the block's waves in step (a barrier per z
   // row, p.lockstep), so neighbouring waves read the cache lines they share
   // while both are in L2.  Every wave of such a block makes the same trips:
@@ -394,8 +400,8 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
   // counter is in order): 512x128x256 0.498 -> 0.481 ms.  The 16-bit launches
   // measured no gain (BF16 a loss) and keep the loads at the top of the loop.
   constexpr bool kPipe = STATS && V == 1 && SB == 4;
-  if (kPipe && wave_live && z0 < nz && p.lw > 0) load_row(z0);
-  for (int it = 0; it < ((wave_live || lockstep) ? p.lw : 0); ++it) {
+  if (kPipe && wave_live && z0 < nz && trips > 0) load_row(z0);
+  for (int it = 0; it < ((wave_live || lockstep) ? trips : 0); ++it) {
     const int z = z0 + it * p.zstep;
     if (lockstep) {
       if (z - wz >= nz) break;
@@ -656,7 +662,7 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
       }
     }
 
-    if (kPipe && it + 1 < p.lw && z + p.zstep < nz) load_row(z + p.zstep);
+    if (kPipe && it + 1 < trips && z + p.zstep < nz) load_row(z + p.zstep);
     if (active) {
 #pragma unroll
       for (int i = 0; i < QN; ++i)

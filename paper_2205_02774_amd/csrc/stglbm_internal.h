@@ -48,6 +48,8 @@ struct StgParams {
 };
 
 // Fused stream-collide pass, one launch per time step.
+constexpr int kMaxZChunks = 64;     // z chunks of a statistics launch with unequal chunks
+
 struct StepParams {
   const void* gin;          // g at step n, [NZ][Q][NY][NX] in the store type
   void* gout;               // g at step n+1
@@ -85,6 +87,10 @@ struct StepParams {
   int stg_blocks;
   int stg_zb;               // blocks of 64 spanwise nodes per plane row group
   StgParams stg;            // that plane: out, tphase[0]
+  // Statistics launches with unequal z chunks (zsched = 1): the blocks of slot
+  // s take z rows zbeg[s] .. zbeg[s + 1] - 1 (multiples of wz rows)
+  int zsched;
+  int zbeg[kMaxZChunks + 1];
 };
 
 // Statistics of 16-bit stores: every launch adds its per-slot sums to FP32

@@ -104,9 +104,10 @@ def test_derive_units_matches_oracle(lib):
     ((512, 128, 256), "f32", 19, 2),     # two z waves per block, 2 x 128 x 16 waves = 4096
     ((512, 128, 256), "f32", 15, 2),
     ((512, 128, 256), "f32", 27, 4),     # one z wave: 4 slots
-    ((512, 128, 256), "f16", 19, 16),    # 16-bit: slots for 16384 waves, 1024 per slot
-    ((512, 128, 256), "bf16", 19, 16),
-    ((1024, 256, 512), "f16", 19, 4),    # 4096 waves per slot
+    ((512, 128, 256), "f16", 19, 12),    # 16-bit, 8-wave blocks: two rounds of 768 resident blocks, 6 slots each
+    ((512, 128, 256), "bf16", 19, 12),
+    ((512, 256, 256), "f16", 19, 6),     # 256 blocks per slot: 3 slots per round
+    ((1024, 256, 512), "f16", 19, 4),    # 512 blocks per slot (768 is no multiple): slots for 16384 waves
     ((64, 32, 32), "f32", 19, 16),       # capped at NZ / 2 for two z waves
     ((64, 32, 32), "f16", 19, 32),       # capped at NZ
 ])

@@ -286,9 +286,10 @@ def test_full_size_statistics_front_parity(cfg_index, qset, steps):
     Each statistics launch shape passes through here with many z rows per
     wave: FP32 D3Q19 (whole-row blocks of two z waves, 128-row chunks, 2 FP64
     slots), FP32 D3Q27 (one z wave, 64-row chunks, 4 slots) and FP16 (one z
-    wave; 16-row chunks and 16 slots at 512x128x256, 128-row chunks and 4
-    slots at 1024x256x512; FP32 window sums folded into FP64 after the 16th
-    sampled step, which the 20-step case crosses).  From rest, after K sampled steps the bins
+    wave; at 512x128x256 the two-round schedule of 12 unequal chunks, 6 x 24,
+    4 x 22 and 2 x 12 rows, one slot each; 128-row chunks and 4 slots at
+    1024x256x512; FP32 window sums folded into FP64 after the 16th sampled
+    step, which the 20-step case crosses).  From rest, after K sampled steps the bins
     x <= K match an oracle channel of 2K + 2 planes with the same inlet (as in
     the front test above), and every bin beyond K sums a velocity that is
     exactly zero.  FP32: the 1e-6 bar.  FP16: each step's rounding of g moves
@@ -499,3 +500,40 @@ def test_inlet_mach_guard_reported():
     print(f"[gpu] inlet guard: {e.value}", flush=True)
     assert e.value.code == abi.E_UNSTABLE and "inlet velocity" in str(e.value)
     lat.close()
+
+
+@pytest.mark.parametrize("store", ["f16", "bf16"])
+def test_unequal_z_chunks_match_uniform_chunks(store, monkeypatch):
+    """The two-round schedule of unequal z chunks (512 x 64 x 96: 24 chunks of
+    5, 4 or 3 and 2 rows) changes only how the statistics are partitioned: f
+    is bit-identical to a run with uniform chunks (tuning override
+    STGLBM_ZCHUNKS=uniform), the sample count is the same, and the statistics
+    agree to FP32 rounding of their window sums (1e-6 normwise).  A run with
+    an explicit schedule (STGLBM_ZCHUNKS) agrees the same way."""
+    from paper_2205_02774_amd import Lattice
+    from oracle.lattice import W
+    nx, ny, nz = 512, 64, 96
+    runs = {}
+    for mode in ("default", "uniform", "40,30,20,6"):
+        if mode == "default":
+            monkeypatch.delenv("STGLBM_ZCHUNKS", raising=False)
+        else:
+            monkeypatch.setenv("STGLBM_ZCHUNKS", mode)
+        print(f"[gpu] z chunks {mode} {store} {(nx, ny, nz)}", flush=True)
+        lat = Lattice(nx, ny, nz, device="cuda:0", store=store, periodic_x=True, nu_lb=2e-2, cs_smag=0.1,
+                      force=(1e-5, 0.0, 0.0))
+        rng = np.random.default_rng(31)
+        lat.set_f(W[:, None, None, None] * (1.0 + 1e-2 * rng.uniform(-1, 1, (19, nz, ny, nx))))
+        lat.stats_reset()
+        lat.step(20)
+        st, n = lat.get_stats()
+        runs[mode] = (lat.get_f(), st, n)
+        lat.close()
+    f0, st0, n0 = runs["uniform"]
+    for mode in ("default", "40,30,20,6"):
+        f1, st1, n1 = runs[mode]
+        nrm = np.linalg.norm(st1 - st0) / np.linalg.norm(st0)
+        print(f"[gpu] z chunks {mode} vs uniform ({store}): statistics normwise {nrm:.3e}", flush=True)
+        assert n1 == n0 == 20
+        np.testing.assert_array_equal(f1, f0)
+        assert nrm < 1e-6
