@@ -97,36 +97,62 @@ const char* check_desc(const stglbm_lattice_desc* d) {
 
 // Statistics launches of 16-bit stores in whole-row blocks of 8 waves: MI355X
 // holds 3 such blocks per compute unit (the kernel stays at <= 80 VGPRs), 768
-// on its 256 CUs.  When that is a whole number spr >= 3 of slots (blocks per
-// slot = base, the x groups times NY), the z rows are cut into 2 spr chunks
-// that fill exactly two rounds of resident blocks: spr long chunks first,
-// spr - 2 slightly shorter ones, then 2 short ones, which go to the positions
-// that free up last.  The short chunks are about half a mean chunk; fewer
-// slots than the uniform rule's (12 against 16 on 512x128x256) mean fewer
-// window-sum bytes per launch.  Measured on 512x128x256 FP16 (ms per step,
-// one box): 24 x 6, 22 x 4, 12 x 2 rows 0.2575 against 0.2633 for 16 chunks
-// of 16; neighbours of that schedule 0.2578-0.2586; 11 chunks (a round of 5
-// slots) 0.272.  Returns false (uniform chunks) where the rule does not apply.
-bool make_two_round_schedule(const stglbm_lattice_desc* d, Layout& L, int base) {
+// on its 256 CUs.  Their z chunks are cut unequal, longest first, so that the
+// blocks dispatched last are short and the launch's tail is short too.
+//
+// When 768 is a whole number spr >= 3 of slots (blocks per slot = base, the
+// x groups times NY), the z rows go into 2 spr chunks that fill exactly two
+// rounds of resident blocks: spr long chunks first, spr - 2 slightly shorter
+// ones, then 2 short ones (about half a mean chunk), which the positions
+// that free up last take.  Fewer slots than the uniform rule's (12 against 16
+// on 512x128x256) also mean fewer window-sum bytes per launch.  Measured on
+// 512x128x256 FP16 (ms per step, one box): 24 x 6, 22 x 4, 12 x 2 rows 0.2575
+// against 0.2633 for 16 chunks of 16; neighbours of that schedule
+// 0.2578-0.2586; 11 chunks (a round of 5 slots) 0.272.
+//
+// Otherwise, where the uniform rule's S chunks make at least two rounds of
+// blocks, the first half of them are long and the rest 0.6 of that length.
+// Measured on 1024x256x512 FP16 (base 512, 4 chunks): 160, 160, 96, 96 rows
+// 2.067 ms per step against 2.098 for 4 x 128 (120, 120, 104, 104, 64: 2.064;
+// 96 x 4, 64 x 2: 2.067; 200, 200, 112: 2.088; 176, 176, 160: 2.108).
+//
+// Returns false (uniform chunks) where neither applies.
+bool make_chunk_schedule(const stglbm_lattice_desc* d, Layout& L, int base) {
   constexpr int kResident = 3 * 256;
-  if (d->store == STGLBM_F32 || L.wz != 1 || L.wx * L.wz != 8 || base <= 0 || kResident % base != 0) return false;
-  const int spr = kResident / base, n = 2 * spr, nz = d->nz;
-  if (spr < 3 || n > kMaxZChunks || nz < 4 * (n - 1)) return false;
-  const int small = (nz + (n - 1)) / (2 * (n - 1));                 // about half of nz / (n - 1)
-  const int rest = nz - 2 * small;
-  const int c1 = (rest + (n - 2) - 1) / (n - 2);                    // first round, rounded up
-  const int r2 = rest - spr * c1;                                   // rows left for the spr - 2 middle chunks
-  if (r2 < (spr - 2) * small) return false;
+  if (d->store == STGLBM_F32 || L.wz != 1 || L.wx * L.wz != 8 || base <= 0) return false;
+  const int nz = d->nz;
   int chunk[kMaxZChunks];
-  for (int i = 0; i < spr; ++i) chunk[i] = c1;
-  for (int i = 0; i < spr - 2; ++i) chunk[spr + i] = r2 / (spr - 2) + (i < r2 % (spr - 2) ? 1 : 0);
-  chunk[n - 2] = chunk[n - 1] = small;
+  int n = 0;
+  if (kResident % base == 0 && kResident / base >= 3) {
+    const int spr = kResident / base;
+    n = 2 * spr;
+    if (n > kMaxZChunks || nz < 4 * (n - 1)) return false;
+    const int small = (nz + (n - 1)) / (2 * (n - 1));               // about half of nz / (n - 1)
+    const int rest = nz - 2 * small;
+    const int c1 = (rest + (n - 2) - 1) / (n - 2);                  // first round, rounded up
+    const int r2 = rest - spr * c1;                                 // rows left for the spr - 2 middle chunks
+    if (r2 < (spr - 2) * small) return false;
+    for (int i = 0; i < spr; ++i) chunk[i] = c1;
+    for (int i = 0; i < spr - 2; ++i) chunk[spr + i] = r2 / (spr - 2) + (i < r2 % (spr - 2) ? 1 : 0);
+    chunk[n - 2] = chunk[n - 1] = small;
+  } else {
+    n = L.slots;
+    if (n < 2 || n > kMaxZChunks || static_cast<long long>(base) * n < 2 * kResident) return false;
+    const int h = (n + 1) / 2, t = n - h;
+    const int a = static_cast<int>(std::lround(nz / (h + 0.6 * t)));
+    const int r = nz - a * h;                                       // rows of the t short chunks
+    if (a < 2 || r < t || r > a * t) return false;
+    for (int i = 0; i < h; ++i) chunk[i] = a;
+    for (int i = 0; i < t; ++i) chunk[h + i] = r / t + (i < r % t ? 1 : 0);
+  }
   L.zbeg[0] = 0;
   for (int i = 0; i < n; ++i) L.zbeg[i + 1] = L.zbeg[i] + chunk[i];
   if (L.zbeg[n] != nz) return false;
+  int longest = 0;
+  for (int i = 0; i < n; ++i) longest = std::max(longest, chunk[i]);
   L.zsched = 1;
   L.slots = n;
-  L.lw = c1;
+  L.lw = longest;
   return true;
 }
 
@@ -176,15 +202,15 @@ Layout make_layout(const stglbm_lattice_desc* d) {
     // wave slots, so all its waves run in step and finish together), 2 slots,
     // more where the grid would hold fewer than 4096 waves.  Other FP32 sets:
     // one z wave, 4 slots.  16-bit stores: one z wave and as many slots as
-    // make 16384 waves, unless the two-round schedule applies (see
-    // make_two_round_schedule).  Measured on MI355X, 512x128x256: FP32 0.455 ms (two
-    // z waves and 4 slots 0.457; one z wave: 4 slots 0.476, 8: 0.482, 16: 0.494;
-    // half rows with four z waves 0.477-0.479); with one z wave the two
-    // 8-wave blocks sharing a CU ran at different speeds, and the first to
-    // finish left the CU half empty for the last 10-25 % of the launch.
-    // FP16 (16 slots) 0.273 ms (8 slots 0.274, 4 slots 0.278, two z waves
-    // 0.298, half rows 0.299); 1024x256x512 FP16 (4 slots) 2.098 ms (8 slots
-    // 2.103, 16 slots 2.143, 2 slots 2.171): both best at 16384 waves.
+    // make 16384 waves, then cut unequal (make_chunk_schedule).  Measured on
+    // MI355X, 512x128x256: FP32 0.455 ms (two z waves and 4 slots 0.457; one
+    // z wave: 4 slots 0.476, 8: 0.482, 16: 0.494; half rows with four z waves
+    // 0.477-0.479); with one z wave the two 8-wave blocks sharing a CU ran at
+    // different speeds, and the first to finish left the CU half empty for
+    // the last 10-25 % of the launch.  Uniform chunks, FP16 with FP64 slots:
+    // 16 slots 0.273 ms (8 slots 0.274, 4 slots 0.278, two z waves 0.298,
+    // half rows 0.299); 1024x256x512 FP16 (4 slots) 2.098 ms (8 slots 2.103,
+    // 16 slots 2.143, 2 slots 2.171): both best at 16384 waves.
     const bool f32 = d->store == STGLBM_F32;
     if (L.short_chunks_when_idle && step_max_waves(store_bytes(d->store), set_size(d), vec, true) == kMaxWavesWide) wz = 2;
     L.wz = wz;
@@ -200,7 +226,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   L.slots = (d->nz + wz * lw - 1) / (wz * lw);
   const char* zenv = std::getenv("STGLBM_ZCHUNKS");   // "r0,r1,...": z rows per chunk, or "uniform" (tuning override)
   if (!zenv) {
-    if (lw_default) make_two_round_schedule(d, L, base);
+    if (lw_default) make_chunk_schedule(d, L, base);
   } else if (std::strcmp(zenv, "uniform") != 0) {
     int beg[kMaxZChunks + 1] = {0}, n = 0, maxc = 0;
     bool ok = true;
