@@ -369,6 +369,9 @@ def main():
     ap.add_argument("--workload", default="channel-512x128x256")
     ap.add_argument("--variants", default="f16,bf16", help="extra store types timed on the same workload")
     ap.add_argument("--variant-warmup", type=int, default=2000)
+    ap.add_argument("--variant-steps", type=int, default=500,
+                    help="timed steps of each store and lattice variant (a window of a few steps is dominated by "
+                         "the fixed latency at its start and end)")
     ap.add_argument("--lattice-variants", default="15:regularized,27:regularized,19:bgk",
                     help="velocity-set:operator pairs timed (FP32) on the same workload ('' = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -411,20 +414,20 @@ def main():
     main_run = run_variant(cfg, cfg["store"], args.steps, args.warmup)
     variants = {}
     for v in [s for s in args.variants.split(",") if s]:
-        r = run_variant(cfg, v, args.steps, args.variant_warmup)
+        r = run_variant(cfg, v, args.variant_steps, args.variant_warmup)
         variants[v] = {
             "value": round(r["mlups"], 1), "ms_per_step": round(r["ms_per_step"], 5),
             "step_kernel_ms": round(r["step_kernel_ms"], 5),
             "roofline_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
             "planes_in_step_kernel": r["planes_in_step_kernel"],
             "speedup_vs_f32": round(r["mlups"] / main_run["mlups"], 3),
-            "warmup": args.variant_warmup,
+            "steps": args.variant_steps, "warmup": args.variant_warmup,
         }
     lattice_variants = {}
     for spec in [v for v in args.lattice_variants.split(",") if v]:
         q, op = spec.split(":")
         try:
-            r = run_variant(cfg, "f32", args.steps, args.variant_warmup, velocity_set=int(q), collision=op)
+            r = run_variant(cfg, "f32", args.variant_steps, args.variant_warmup, velocity_set=int(q), collision=op)
         except abi.StglbmError as e:            # e.g. plain BGK going unstable at tau0 - 1/2 = 3.4e-3
             log(f"[bench] D3Q{q} {op}: {e}")
             import torch
@@ -435,7 +438,7 @@ def main():
             "value": round(r["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r["ms_per_step"], 5),
             "step_kernel_ms": round(r["step_kernel_ms"], 5), "algorithmic_bytes_per_cell": 2 * int(q) * 4,
             "achieved_gbs": round(r["achieved_gbs"], 1), "roofline_frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
-            "warmup": args.variant_warmup}
+            "steps": args.variant_steps, "warmup": args.variant_warmup}
     large = large_lattice(args.large, args.large_steps, args.large_warmup) if args.large else None
     periodic = periodic_reference(cfg["nx"], cfg["ny"], cfg["nz"], args.periodic_steps, 500) \
         if args.periodic_steps > 0 else None

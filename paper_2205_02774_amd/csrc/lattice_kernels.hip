@@ -35,6 +35,24 @@ __global__ void stats_sum_kernel(const double* d, int nd, const float* f, int nf
   }
 }
 
+// The fold of up to K window slots: every slot's value is loaded before the
+// first add (the generic loop above waits for one load per slot in turn), then
+// added to the FP64 total in slot order.
+template <int K>
+__global__ void stats_fold_kernel(const float* __restrict__ f, int nf, long long n, double* __restrict__ out) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
+    float x[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) x[k] = k < nf ? f[k * n + e] : 0.0f;
+    double v = out[e];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (k < nf) v += static_cast<double>(x[k]);
+    out[e] = v;
+  }
+}
+
 __global__ void copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst, unsigned long long n16) {
   const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
   for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
@@ -249,7 +267,14 @@ hipError_t launch_step(const StepParams& p, int store, bool stats, hipStream_t s
 
 hipError_t launch_stats_sum(const double* d, int nd, const float* f, int nf, long long n, double* out, bool add,
                             hipStream_t s) {
-  stats_sum_kernel<<<grid_for(static_cast<unsigned long long>(n), 256), 256, 0, s>>>(d, nd, f, nf, n, out, add);
+  const int grid = grid_for(static_cast<unsigned long long>(n), 256);
+  if (nd == 0 && add && nf >= 1 && nf <= 32) {
+    // the window fold: all slots' loads in flight at once
+    if (nf <= 16) stats_fold_kernel<16><<<grid, 256, 0, s>>>(f, nf, n, out);
+    else stats_fold_kernel<32><<<grid, 256, 0, s>>>(f, nf, n, out);
+    return hipGetLastError();
+  }
+  stats_sum_kernel<<<grid, 256, 0, s>>>(d, nd, f, nf, n, out, add);
   return hipGetLastError();
 }
 
