@@ -107,7 +107,10 @@ def test_derive_units_matches_oracle(lib):
     ((512, 128, 256), "f16", 19, 12),    # 16-bit, 8-wave blocks: two rounds of 768 resident blocks, 6 slots each
     ((512, 128, 256), "bf16", 19, 12),
     ((512, 256, 256), "f16", 19, 6),     # 256 blocks per slot: 3 slots per round
+    ((512, 64, 96), "f16", 19, 24),      # 64 blocks per slot: 12 per round, 24 chunks of 5, 4 or 3 and 2 rows
+    ((512, 64, 64), "f16", 19, 32),      # too few rows for 24 chunks: the uniform rule's 32, cut unequal
     ((1024, 256, 512), "f16", 19, 4),    # 512 blocks per slot (768 is no multiple): slots for 16384 waves
+    ((448, 128, 256), "f16", 19, 19),    # 7-wave rows: uniform chunks (16384 waves: 19 slots of 14 rows)
     ((64, 32, 32), "f32", 19, 16),       # capped at NZ / 2 for two z waves
     ((64, 32, 32), "f16", 19, 32),       # capped at NZ
 ])
