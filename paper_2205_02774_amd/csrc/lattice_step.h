@@ -353,6 +353,7 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
   int z0 = slot * p.wz * (p.zstep == p.wz ? p.lw : 1) + wz;
   int trips = p.lw;
   if (STATS && p.zsched) {
+    // unequal chunks, longest first: slot s takes rows zbeg[s] .. zbeg[s + 1] - 1
     const int zb = p.zbeg[slot], ze = p.zbeg[slot + 1];
     z0 = zb + wz;
     trips = (ze - zb) / p.wz;
