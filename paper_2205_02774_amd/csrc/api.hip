@@ -51,7 +51,7 @@ struct TraceRange {
 
 struct Layout {
   uint64_t g[2] = {0, 0}, stats = 0, win = 0, sponge = 0, flag = 0, ubc = 0, rans = 0, rows = 0, modes = 0,
-           sqrtq = 0, arow = 0, bz = 0, sig = 0, scalars = 0, total = 0;
+           sqrtq = 0, arow = 0, bz = 0, sig = 0, ptab = 0, scalars = 0, total = 0;
   int vec = 1, nxt = 0, wx = 1, wz = 1, nxg = 0, slots = 0, lw = 0, zstep = 1, nblocks = 0;
   bool short_chunks_when_idle = true;   // steps without statistics: their own shape
   int wx_idle = 1, nxg_idle = 1, lw_idle = 1;
@@ -94,6 +94,10 @@ const char* check_desc(const stglbm_lattice_desc* d) {
     if (!std::isfinite(d->force[a])) return "force must be finite";
   return nullptr;
 }
+
+// Rows of the row-phasor table: NY rounded up to a multiple of 8 (the most
+// rows a plane block takes), so a block's last row group stays inside.
+int ptab_rows(int ny) { return (ny + 7) / 8 * 8; }
 
 // Statistics launches of 16-bit stores in whole-row blocks of 8 waves: MI355X
 // holds 3 such blocks per compute unit (the kernel stays at <= 80 VGPRs), 768
@@ -289,6 +293,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
     L.arow = take(static_cast<uint64_t>(d->ny) * d->max_modes * 2 * sizeof(double));
     L.bz = take(static_cast<uint64_t>(d->max_modes) * d->nz * sizeof(float2));
     L.sig = take(static_cast<uint64_t>(d->max_modes) * sizeof(float4));
+    L.ptab = take(static_cast<uint64_t>(kStgBatch) * d->max_modes * ptab_rows(d->ny) * sizeof(float2));
     L.scalars = take(kScalars * sizeof(double));
   }
   L.total = off;
@@ -346,6 +351,11 @@ struct stglbm_ctx {
   // stream-collide launch (ring_n = 0: none valid).
   int64_t ring_t0 = 0, ring_base = 0;
   int ring_n = 0;
+  // Row phasors of the steps ptab_t0 .. ptab_t0 + ptab_n - 1, in the table of
+  // kStgBatch slots (step t in slot (t - ptab_base) mod kStgBatch), which the
+  // plane kernel and the trailing plane blocks read (ptab_n = 0: none valid).
+  int64_t ptab_t0 = 0, ptab_base = 0;
+  int ptab_n = 0;
 
   template <class T> T* at(uint64_t off) { return reinterpret_cast<T*>(ws + off); }
   void* gbuf(int k) { return ws + L.g[k]; }
@@ -468,8 +478,12 @@ StgParams stg_params(stglbm_t h, int64_t t_first, int n, float* out) {
   s.sig = h->at<float4>(h->L.sig);
   s.rows = h->at<double>(h->L.rows);
   s.out = out;
+  s.ptab = h->at<float2>(h->L.ptab);
+  s.ptab_rows = ptab_rows(h->d.ny);
   s.ny = h->d.ny; s.nz = h->d.nz; s.n_modes = h->n_modes;
   s.n_planes = n;
+  for (int b = 0; b < n; ++b)
+    s.pslot[b] = static_cast<int>(((t_first + b - h->ptab_base) % kStgBatch + kStgBatch) % kStgBatch);
   s.c_x = h->c_x;
   s.conv = h->c_t / h->c_x;
   const double kTwoPi = 6.283185307179586476925;
@@ -478,9 +492,22 @@ StgParams stg_params(stglbm_t h, int64_t t_first, int n, float* out) {
   return s;
 }
 
+// Row phasors of the steps t_first .. t_first + n - 1 (n <= kStgBatch) in the
+// table; if any is missing, those of the kStgBatch steps from t_first are made
+// first (one small launch, on the handle's stream before their readers).
+int ensure_row_phases(stglbm_t h, int64_t t_first, int n) {
+  if (h->ptab_n > 0 && t_first >= h->ptab_t0 && t_first + n <= h->ptab_t0 + h->ptab_n) return STGLBM_OK;
+  h->ptab_n = 0;
+  h->ptab_t0 = h->ptab_base = t_first;
+  HIP_CHECK(h, launch_stg_time_phase(stg_params(h, t_first, kStgBatch, nullptr), h->stream), "STG row-phase launch");
+  h->ptab_n = kStgBatch;
+  return STGLBM_OK;
+}
+
 // STG planes of the n consecutive steps t_first .. t_first + n - 1, written
 // one after the other to out (n <= kStgBatch), in one launch.
 int launch_planes(stglbm_t h, int64_t t_first, int n, float* out, bool timed_ok = true) {
+  if (int rc = ensure_row_phases(h, t_first, n)) return rc;
   const StgParams s = stg_params(h, t_first, n, out);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = timed_ok && h->prof;
@@ -528,6 +555,7 @@ int step_once(stglbm_t h, const float* plane, bool timed_ok, bool ring_ahead = f
   if (tail) {
     p.stg_zb = (h->d.nz + 63) / 64;
     p.stg_blocks = p.stg_zb * ((h->d.ny + kStgTailRows - 1) / kStgTailRows);
+    if (int rc = ensure_row_phases(h, t2, 1)) return rc;
     p.stg = stg_params(h, t2, 1, ring_slot(h, t2));
   }
   const bool window = h->sampling && h->d.store != STGLBM_F32;
@@ -740,6 +768,7 @@ int stglbm_set_rans_inlet(stglbm_t h, const stglbm_rans_inlet* in) {
   h->inlet_hash = hs;
   h->inlet_ready = true;
   h->ring_n = 0;
+  h->ptab_n = 0;
   return rc;
 }
 
@@ -1020,6 +1049,7 @@ int stglbm_set_stream(stglbm_t h, void* hip_stream) {
   HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   h->stream = static_cast<hipStream_t>(hip_stream);
   h->ring_n = 0;   // planes made on the old stream are not ordered before work on the new one
+  h->ptab_n = 0;
   return STGLBM_OK;
 }
 
@@ -1079,6 +1109,7 @@ int stglbm_restore(stglbm_t h, const void* h_buf, uint64_t n) {
   HIP_CHECK(h, hipStreamSynchronize(h->stream), "hipStreamSynchronize");
   h->t = hd.t;
   h->ring_n = 0;
+  h->ptab_n = 0;
   h->n_samples = hd.n_samples;
   h->sampling = hd.sampling != 0;
   return STGLBM_OK;

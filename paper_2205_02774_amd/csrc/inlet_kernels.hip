@@ -217,7 +217,7 @@ __global__ void inlet_rowphase_kernel(SetupParams p) {
   double s, c;
   sincos(md[0] * md[2] * ((j + 0.5) * p.c_x) + md[7], &s, &c);
   const double a = sqrt6 * p.sqrtq[e];
-  p.arow[e] = make_double2(a * c, a * s);
+  p.arow[(long long)m * p.ny + j] = make_double2(a * c, a * s);   // [mode][row]
 }
 
 // Spanwise phasors exp(i k^n d^n_z z_k), z_k = k c_x, FP64 -> FP32.
@@ -234,17 +234,37 @@ __global__ void inlet_zphase_kernel(SetupParams p) {
     p.sig[m] = make_float4(static_cast<float>(md[4]), static_cast<float>(md[5]), static_cast<float>(md[6]), 0.0f);
 }
 
+// Row phasors of n_planes consecutive steps into their table slots (grid y =
+// plane): P[slot][m][j] = a[m][j] exp(i 2 pi d_x (x_in - U_b t) / L_e), the
+// FP64 product rounded once to FP32; rows past NY (up to ptab_rows) are zero.
+// A block takes 32 modes: their time factors (one FP64 sincos each) in LDS,
+// then the rows of each mode, consecutive threads on consecutive rows.
+__global__ __launch_bounds__(256) void stg_time_phase_kernel(StgParams p) {
+  __shared__ double2 G[32];
+  const int b = blockIdx.y;
+  const int m0 = blockIdx.x * 32;
+  const int cnt = min(32, p.n_modes - m0);
+  if (static_cast<int>(threadIdx.x) < cnt) {
+    double sn, cs;
+    sincos(p.modes[(long long)(m0 + threadIdx.x) * kModeFields + 1] * p.tphase[b], &sn, &cs);
+    G[threadIdx.x] = make_double2(cs, sn);
+  }
+  __syncthreads();
+  float2* out = p.ptab + ((long long)p.pslot[b] * p.n_modes + m0) * p.ptab_rows;
+  for (int e = threadIdx.x; e < cnt * p.ptab_rows; e += blockDim.x) {
+    const int mm = e / p.ptab_rows, j = e - mm * p.ptab_rows;
+    out[e] = j < p.ny ? stg_row_phasor(p.arow[(long long)(m0 + mm) * p.ny + j], G[mm]) : make_float2(0.f, 0.f);
+  }
+}
+
 // Inlet planes of n_planes consecutive steps (grid z), kStgRows rows x 64
 // spanwise nodes per block (stg_block.h); kStgRows is chosen so that the grid
 // still has >= 2048 waves.  The inlet guard |u_x| < 0.3 c_s is applied where a
 // plane is used, by the step kernel.
 template <int kStgRows>
 __global__ __launch_bounds__(64 * kStgWaves) void stg_plane_kernel(StgParams p) {
-  // modes staged per pass: the row phasors and sigma of the last pass are
-  // dead when the partial sums meet, so the two share LDS (under 64 KiB)
-  constexpr int kChunk = kStgChunk * 2 / (kStgRows >= 2 ? kStgRows : 2);
-  __shared__ __attribute__((aligned(16))) char smem[stg_block_lds<kStgRows, kChunk>()];
-  stg_plane_block<kStgRows, kChunk, 8>(p, blockIdx.z, blockIdx.x, blockIdx.y, threadIdx.x, threadIdx.y, smem);
+  __shared__ __attribute__((aligned(16))) char smem[stg_block_lds<kStgRows>()];
+  stg_plane_block<kStgRows, kStgInFlight>(p, blockIdx.z, blockIdx.x, blockIdx.y, threadIdx.x, threadIdx.y, smem);
 }
 
 }  // namespace
@@ -262,6 +282,13 @@ hipError_t launch_inlet_setup(const SetupParams& p, hipStream_t s) {
   if (e != hipSuccess) return e;
   const long long nr = (long long)p.n_modes * p.ny;
   inlet_rowphase_kernel<<<static_cast<unsigned>((nr + 255) / 256), 256, 0, s>>>(p);
+  return hipGetLastError();
+}
+
+hipError_t launch_stg_time_phase(const StgParams& p, hipStream_t s) {
+  if (p.n_planes < 1 || p.n_planes > kStgBatch || p.ptab_rows < p.ny) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((p.n_modes + 31) / 32), static_cast<unsigned>(p.n_planes));
+  stg_time_phase_kernel<<<grid, 256, 0, s>>>(p);
   return hipGetLastError();
 }
 

@@ -275,8 +275,8 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
     extern __shared__ __attribute__((aligned(16))) char stg_smem[];
     const int item = blockIdx.x - p.nblocks;
     const int w = (threadIdx.x >> 6) + (blockDim.x >> 6) * threadIdx.y;
-    stg_plane_block<kStgTailRows, kStgTailChunk, kStgTailInFlight>(p.stg, 0, item % p.stg_zb, item / p.stg_zb,
-                                                                   threadIdx.x & 63, w, stg_smem);
+    stg_plane_block<kStgTailRows, kStgTailInFlight>(p.stg, 0, item % p.stg_zb, item / p.stg_zb, threadIdx.x & 63, w,
+                                                    stg_smem);
     return;
   }
   using Vec = Raw<V * SB>;
@@ -730,7 +730,7 @@ hipError_t launch_step_v(const StepParams& p, bool stats, hipStream_t s) {
     return hipErrorInvalidValue;
   const dim3 grid(p.nblocks + p.stg_blocks);
   size_t lds = (stats && p.wz > 1) ? sizeof(float) * 9 * 64 * V * p.wx * p.wz : 0;
-  constexpr size_t kStgLds = stg_block_lds<kStgTailRows, kStgTailChunk>();
+  constexpr size_t kStgLds = stg_block_lds<kStgTailRows>();
   if (p.stg_blocks > 0 && lds < kStgLds) lds = kStgLds;
   if (p.has_force) {
     if (stats) step_kernel<Codec, QN, REG, V, true, true><<<grid, block, lds, s>>>(p);

@@ -11,12 +11,11 @@ constexpr int kModeFields = 8;      // k, d(3), sigma(3), phi
 constexpr int kScalars = 8;         // L_e k_min k_max alpha k_cut clamps U_b N
 constexpr int kMaxWavesPerBlock = 8; // step kernel: waves along x times waves along z
 constexpr int kMaxWavesWide = 16;    // FP32 statistics launches of D3Q15 / D3Q19, one cell per lane
-constexpr int kStgChunk = 1024;     // modes staged in LDS per pass of the STG kernel (2048 / rows for 4 and 8 rows)
+constexpr int kStgInFlight = 8;     // spanwise phasor loads in flight per wave of the plane kernel
 constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
 constexpr int kStgBatch = 16;       // inlet planes per plane-kernel launch; ring of planes made ahead
 constexpr int kStgTailRows = 2;     // rows per plane block of a 16-bit statistics launch
 constexpr int kStgTailInFlight = 2; // spanwise phasor loads in flight per wave there (at most 80 VGPRs)
-constexpr int kStgTailChunk = 256;  // modes staged per pass there (12 KiB of LDS)
 
 // Waves per block a step-kernel instantiation is built for.  The FP32
 // statistics launches of D3Q15 and D3Q19 with one cell per lane fit 16 waves
@@ -35,11 +34,14 @@ constexpr int kFlagInletMach = 2;   // |u_bc,x| >= 0.3 c_s at an inlet node
 // stream-collide launch.
 struct StgParams {
   const double* modes;      // [N][8]
-  const double2* arow;      // [NY][N] sqrt 6 sqrt(q^n) exp(i (k^n d^n_y y_j + phi^n))
+  const double2* arow;      // [N][NY] sqrt 6 sqrt(q^n) exp(i (k^n d^n_y y_j + phi^n))
   const float2* bz;         // [N][NZ] spanwise phasors exp(i k d_z z)
   const float4* sig;        // [N] sigma^n in FP32 (x, y, z, 0)
   const double* rows;       // [NY][18]
   float* out;               // n_planes planes [NY][NZ][3], one after the other
+  float2* ptab;             // row phasors of kStgBatch steps: [slot][N][ptab_rows] FP32, rows past NY zero
+  int ptab_rows;            // NY rounded up to a multiple of 8
+  int pslot[kStgBatch];     // table slot of each plane
   int ny, nz, n_modes;
   int n_planes;             // 1 .. kStgBatch consecutive steps
   double c_x;               // lattice spacing (m)
@@ -118,7 +120,7 @@ struct SetupParams {
   double* rows;             // [NY][18]
   double* modes;            // [N][8]
   double* sqrtq;            // [NY][N]
-  double2* arow;            // [NY][N] time-independent row phasors of the plane kernel
+  double2* arow;            // [N][NY] time-independent row phasors of the plane kernel
   float2* bz;               // [N][NZ]
   float4* sig;              // [N]
   double* scalars;          // [8]
@@ -127,6 +129,9 @@ struct SetupParams {
 
 hipError_t launch_step(const StepParams& p, int store, bool stats, hipStream_t s);
 hipError_t launch_step_variant(const StepParams& p, int store, bool stats, hipStream_t s);
+// Row phasors of p.n_planes steps into the table slots p.pslot (before any
+// plane kernel or trailing block that reads them).
+hipError_t launch_stg_time_phase(const StgParams& p, hipStream_t s);
 hipError_t launch_stg(const StgParams& p, hipStream_t s);
 hipError_t launch_inlet_setup(const SetupParams& p, hipStream_t s);
 hipError_t launch_fill_zero(void* ptr, unsigned long long bytes, hipStream_t s);

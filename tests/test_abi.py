@@ -70,11 +70,13 @@ def test_descriptor_validation_and_footprint(lib):
     g32 = 2 * 19 * 512 * 128 * 256 * 4
     bins = 9 * 512 * 128 * 8                          # one FP64 statistics slot
     ring = 16 * 128 * 256 * 3 * 4                     # inlet planes of 16 steps, FP32
-    assert fp >= g32
-    # two distribution buffers + FP64 statistics slots (at most 16) + the plane ring + the small inlet tables
-    assert fp - g32 <= 16 * bins + ring + 4 * 2 ** 20
+    ptab = 16 * 600 * 128 * 8                         # row phasors of 16 steps, [mode][row] FP32 pairs
+    assert fp >= g32 + ring + ptab
+    # two distribution buffers + FP64 statistics slots (at most 16) + the plane ring and row-phasor
+    # table + the small inlet tables
+    assert fp - g32 <= 16 * bins + ring + ptab + 4 * 2 ** 20
     d16 = make_desc(512, 128, 256, nu_lb=1.1458e-3, store="f16", max_modes=600, max_rans=96)
-    assert 0 <= footprint(d16) - g32 // 2 <= 16 * bins + ring + 4 * 2 ** 20
+    assert 0 <= footprint(d16) - g32 // 2 <= 16 * bins + ring + ptab + 4 * 2 ** 20
     bad = make_desc(1, 128, 256, nu_lb=1e-3, max_modes=10, max_rans=10)
     with pytest.raises(abi.StglbmError) as e:
         footprint(bad)
