@@ -237,23 +237,40 @@ __global__ void inlet_zphase_kernel(SetupParams p) {
 // Row phasors of n_planes consecutive steps into their table slots (grid y =
 // plane): P[slot][m][j] = a[m][j] exp(i 2 pi d_x (x_in - U_b t) / L_e), the
 // FP64 product rounded once to FP32; rows past NY (up to ptab_rows) are zero.
-// A block takes 32 modes: their time factors (one FP64 sincos each) in LDS,
-// then the rows of each mode, consecutive threads on consecutive rows.
+// A block takes kTimePhaseModes modes: their time factors (one FP64 sincos
+// each) in LDS, then the rows of each mode, consecutive threads on
+// consecutive rows, each thread's loads issued before its first product.
+constexpr int kTimePhaseModes = 8;
+
 __global__ __launch_bounds__(256) void stg_time_phase_kernel(StgParams p) {
-  __shared__ double2 G[32];
+  constexpr int kPer = 4;
+  __shared__ double2 G[kTimePhaseModes];
   const int b = blockIdx.y;
-  const int m0 = blockIdx.x * 32;
-  const int cnt = min(32, p.n_modes - m0);
+  const int m0 = blockIdx.x * kTimePhaseModes;
+  const int cnt = min(kTimePhaseModes, p.n_modes - m0);
   if (static_cast<int>(threadIdx.x) < cnt) {
     double sn, cs;
     sincos(p.modes[(long long)(m0 + threadIdx.x) * kModeFields + 1] * p.tphase[b], &sn, &cs);
     G[threadIdx.x] = make_double2(cs, sn);
   }
   __syncthreads();
-  float2* out = p.ptab + ((long long)p.pslot[b] * p.n_modes + m0) * p.ptab_rows;
-  for (int e = threadIdx.x; e < cnt * p.ptab_rows; e += blockDim.x) {
-    const int mm = e / p.ptab_rows, j = e - mm * p.ptab_rows;
-    out[e] = j < p.ny ? stg_row_phasor(p.arow[(long long)(m0 + mm) * p.ny + j], G[mm]) : make_float2(0.f, 0.f);
+  const int rows = p.ptab_rows, total = cnt * rows;
+  const double2* a = p.arow + (long long)m0 * p.ny;
+  float2* out = p.ptab + ((long long)p.pslot[b] * p.n_modes + m0) * rows;
+  for (int e0 = threadIdx.x; e0 < total; e0 += kPer * blockDim.x) {
+    double2 av[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = e0 + k * blockDim.x;
+      const int mm = e / rows, j = e - mm * rows;
+      av[k] = e < total && j < p.ny ? a[(long long)mm * p.ny + j] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int e = e0 + k * blockDim.x;
+      const int mm = e / rows, j = e - mm * rows;
+      if (e < total) out[e] = j < p.ny ? stg_row_phasor(av[k], G[mm]) : make_float2(0.f, 0.f);
+    }
   }
 }
 
@@ -287,7 +304,8 @@ hipError_t launch_inlet_setup(const SetupParams& p, hipStream_t s) {
 
 hipError_t launch_stg_time_phase(const StgParams& p, hipStream_t s) {
   if (p.n_planes < 1 || p.n_planes > kStgBatch || p.ptab_rows < p.ny) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<unsigned>((p.n_modes + 31) / 32), static_cast<unsigned>(p.n_planes));
+  const dim3 grid(static_cast<unsigned>((p.n_modes + kTimePhaseModes - 1) / kTimePhaseModes),
+                  static_cast<unsigned>(p.n_planes));
   stg_time_phase_kernel<<<grid, 256, 0, s>>>(p);
   return hipGetLastError();
 }
