@@ -1,8 +1,8 @@
 """Precision pattern: the FP16 deviation store against FP32 and the FP64 oracle,
-judged on long-run channel statistics (64x32x32, 10k warm-up steps, 40k sampled).
+compared on long-run channel statistics (64x32x32, 10k warm-up steps, 40k sampled).
 
 The flow is chaotic, so a run in any precision is a different realisation
-after a few thousand steps (an accepted reading: results are judged on
+after a few thousand steps (an accepted reading: results are compared as
 statistics), and a single run cannot resolve a 1 % bound on the second
 moments: equally valid FP32 realisations differ by several per cent there.
 The stores are therefore compared as ensembles.  Each member starts from
