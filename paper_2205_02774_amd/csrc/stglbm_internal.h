@@ -14,8 +14,8 @@ constexpr int kMaxWavesWide = 16;    // FP32 statistics launches of D3Q15 / D3Q1
 constexpr int kStgInFlight = 8;     // spanwise phasor loads in flight per wave of the plane kernel
 constexpr int kStgWaves = 8;        // waves per STG block, each summing 1/8 of the modes
 constexpr int kStgBatch = 16;       // inlet planes per plane-kernel launch; ring of planes made ahead
-constexpr int kStgTailRows = 2;     // rows per plane block of a 16-bit statistics launch
-constexpr int kStgTailInFlight = 2; // spanwise phasor loads in flight per wave there (at most 80 VGPRs)
+constexpr int kStgTailRows = 4;     // rows per plane block of a 16-bit statistics launch
+constexpr int kStgTailInFlight = 8; // spanwise phasor loads in flight per wave there
 
 // Waves per block a step-kernel instantiation is built for.  The FP32
 // statistics launches of D3Q15 and D3Q19 with one cell per lane fit 16 waves

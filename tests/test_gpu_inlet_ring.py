@@ -91,10 +91,10 @@ def test_planes_from_trailing_blocks(store, shape, monkeypatch):
     a run with the trailing blocks switched off (tuning override
     STGLBM_TAIL_STG=0) bit for bit over 40 steps, across calls of different
     lengths and a statistics restart.  Shapes: a ragged spanwise block (NZ =
-    70 and 33), an odd NY (the last row pair half empty), fewer modes than
-    waves (3: five waves sum nothing) and more modes than one staging pass
-    holds (300 > 256).  (The plane kernel's planes are checked against the
-    oracle's STG in the inlet tests.)"""
+    70 and 33), NY = 7 and 5 (the last row group of a block partly empty),
+    fewer modes than waves (3: five waves sum nothing) and more modes than a
+    wave's loads in flight cover in one round (300).  (The plane kernel's
+    planes are checked against the oracle's STG in the inlet tests.)"""
     from paper_2205_02774_amd import channel_from_config
     nx, ny, nz, modes = shape
     cfg = small_channel(nx, ny, nz, n_modes=modes, seed=9)
