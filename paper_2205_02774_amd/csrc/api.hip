@@ -271,17 +271,12 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   const uint64_t gbytes = static_cast<uint64_t>(set_size(d)) * cells * store_bytes(d->store);
   L.g[0] = take(gbytes);
   L.g[1] = take(gbytes);
-  // Statistics: FP32 stores keep FP64 sums per slot; 16-bit stores keep FP64
-  // totals and FP32 sums per slot over the current window (kStatsWindow
-  // sampled steps).  The two pieces are adjacent, before the sponge table.
+  // Statistics: FP64 totals and FP32 sums per slot over the current window
+  // (kStatsWindow sampled steps).  The two pieces are adjacent, before the
+  // sponge table.
   const uint64_t bins9 = 9ull * d->nx * d->ny;
-  if (d->store == STGLBM_F32) {
-    L.stats = take(static_cast<uint64_t>(L.slots) * bins9 * sizeof(double));
-    L.win = L.stats;
-  } else {
-    L.stats = take(bins9 * sizeof(double));
-    L.win = take(static_cast<uint64_t>(L.slots) * bins9 * sizeof(float));
-  }
+  L.stats = take(bins9 * sizeof(double));
+  L.win = take(static_cast<uint64_t>(L.slots) * bins9 * sizeof(float));
   L.sponge = take(static_cast<uint64_t>(d->nx) * sizeof(float));
   L.flag = take(2 * sizeof(int));
   if (!d->periodic_x) {
@@ -558,7 +553,7 @@ int step_once(stglbm_t h, const float* plane, bool timed_ok, bool ring_ahead = f
     if (int rc = ensure_row_phases(h, t2, 1)) return rc;
     p.stg = stg_params(h, t2, 1, ring_slot(h, t2));
   }
-  const bool window = h->sampling && h->d.store != STGLBM_F32;
+  const bool window = h->sampling;
   if (window) p.win_first = h->n_samples % kStatsWindow == 0 ? 1 : 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = timed_ok && h->prof && (h->prof_count++ % h->prof_every == 0);
@@ -876,32 +871,24 @@ int stglbm_get_stats(stglbm_t h, double* h_out, uint64_t n, int64_t* n_samples) 
   const uint64_t bins = static_cast<uint64_t>(h->d.nx) * h->d.ny;
   if (!h_out || n != bins * 9) return fail(h, STGLBM_E_INVAL, "stats buffer must hold NX*NY*9 doubles");
   const int rc = sync_and_check(h);
-  const bool f32 = h->d.store == STGLBM_F32;
   const size_t n9 = 9 * bins;
-  std::vector<double> raw(f32 ? static_cast<size_t>(h->L.slots) * n9 : n9);
+  std::vector<double> raw(n9);
   HIP_CHECK(h, hipMemcpy(raw.data(), h->at<double>(h->L.stats), raw.size() * sizeof(double), hipMemcpyDeviceToHost),
             "hipMemcpy stats");
-  std::vector<float> win(f32 ? 0 : static_cast<size_t>(h->L.slots) * n9);
-  if (!f32)
-    HIP_CHECK(h, hipMemcpy(win.data(), h->at<float>(h->L.win), win.size() * sizeof(float), hipMemcpyDeviceToHost),
-              "hipMemcpy window sums");
-  // device layout [slot][k][y][x]; API layout [x][y][k].  FP32 stores: the
-  // slots summed in order.  16-bit stores: the totals plus the current
-  // window's slots in order (the fold's own sum, so a later fold gives the same
-  // numbers whenever the statistics are read).
-  const bool open = !f32 && h->n_samples % kStatsWindow != 0;
+  std::vector<float> win(static_cast<size_t>(h->L.slots) * n9);
+  HIP_CHECK(h, hipMemcpy(win.data(), h->at<float>(h->L.win), win.size() * sizeof(float), hipMemcpyDeviceToHost),
+            "hipMemcpy window sums");
+  // device layout [slot][k][y][x]; API layout [x][y][k]: the totals plus the
+  // current window's slots in order (the fold's own sum, so a later fold gives
+  // the same numbers whenever the statistics are read).
+  const bool open = h->n_samples % kStatsWindow != 0;
   for (int x = 0; x < h->d.nx; ++x)
     for (int y = 0; y < h->d.ny; ++y)
       for (int k = 0; k < 9; ++k) {
         const size_t e = static_cast<size_t>(k) * bins + static_cast<size_t>(y) * h->d.nx + x;
-        double v = 0.0;
-        if (f32) {
-          for (int s = 0; s < h->L.slots; ++s) v += raw[static_cast<size_t>(s) * n9 + e];
-        } else {
-          v = raw[e];
-          if (open)
-            for (int s = 0; s < h->L.slots; ++s) v += static_cast<double>(win[static_cast<size_t>(s) * n9 + e]);
-        }
+        double v = raw[e];
+        if (open)
+          for (int s = 0; s < h->L.slots; ++s) v += static_cast<double>(win[static_cast<size_t>(s) * n9 + e]);
         h_out[(static_cast<size_t>(x) * h->d.ny + y) * 9 + k] = v;
       }
   if (n_samples) *n_samples = h->n_samples;

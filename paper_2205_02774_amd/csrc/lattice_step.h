@@ -684,17 +684,16 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
     // LDS.  All 9 slot values are loaded first, before the barrier: a
     // read-modify-write per quantity would make 9 dependent round trips (the
     // stores may alias the later loads as far as the compiler knows).
-    // FP32 stores add to FP64 slot sums; 16-bit stores add to FP32 window
-    // sums (half the bytes), which the host folds into FP64 every
-    // kStatsWindow sampled steps.
-    using Acc = typename std::conditional<SB == 4, double, float>::type;
+    // Each slot holds FP32 sums over a window of kStatsWindow sampled steps
+    // (half the bytes of FP64 slots), which the host folds into FP64 totals
+    // after the window's last step.
+    using Acc = float;
     extern __shared__ float red[];             // [wz][9][64 wx V]
     const int tx = threadIdx.x, bx = 64 * p.wx * V;
     const bool rmw = wz == 0 && active && wave_live;
     const long long sstride = (long long)ny * nx;
-    Acc* const base = SB == 4 ? reinterpret_cast<Acc*>(p.stats) : reinterpret_cast<Acc*>(p.win);
-    Acc* st = base + (long long)slot * 9 * sstride + (long long)y * nx + x0;
-    const bool fresh = SB != 4 && p.win_first;
+    Acc* st = p.win + (long long)slot * 9 * sstride + (long long)y * nx + x0;
+    const bool fresh = p.win_first;
     Acc old[9][V];
     if (rmw) {
 #pragma unroll

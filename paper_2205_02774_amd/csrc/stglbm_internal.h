@@ -80,9 +80,9 @@ struct StepParams {
   float mach_limit;         // inlet guard: |u_bc,x| < 0.3 c_s
   const float* sponge;      // [NX] viscosity multipliers (all 1 if no sponge)
   const float* ubc;         // [NY][NZ][3] inlet velocity of this step (lattice units)
-  double* stats;            // FP32 store: [slots][9][NY][NX] FP64 sums
-  float* win;               // 16-bit stores: [slots][9][NY][NX] FP32 sums of the current window
-  int win_first;            // 16-bit stores: first sampled step of a window (store, not add)
+  double* stats;            // [9][NY][NX] FP64 totals of the closed windows (not written by the kernel)
+  float* win;               // [slots][9][NY][NX] FP32 sums of the current window
+  int win_first;            // first sampled step of a window (store, not add)
   int* flag;
   // Trailing blocks (blockIdx.x >= nblocks) make one inlet plane of a later
   // step while the launch's last lattice blocks finish (0: none).
@@ -95,8 +95,7 @@ struct StepParams {
   int zbeg[kMaxZChunks + 1];
 };
 
-// Statistics of 16-bit stores: every launch adds its per-slot sums to FP32
-// window sums; after kStatsWindow sampled steps (counted from stats_reset) they
+// Statistics: every launch adds its per-slot sums to FP32 window sums; after kStatsWindow sampled steps (counted from stats_reset) they
 // are folded, in slot order, into the FP64 totals [9][NY][NX].
 constexpr int kStatsWindow = 16;
 

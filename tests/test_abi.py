@@ -68,7 +68,7 @@ def test_descriptor_validation_and_footprint(lib):
     d = make_desc(512, 128, 256, nu_lb=1.1458e-3, max_modes=600, max_rans=96)
     fp = footprint(d)
     g32 = 2 * 19 * 512 * 128 * 256 * 4
-    bins = 9 * 512 * 128 * 8                          # one FP64 statistics slot
+    bins = 9 * 512 * 128 * 8                          # the FP64 statistics totals (twice a window slot's bytes)
     ring = 16 * 128 * 256 * 3 * 4                     # inlet planes of 16 steps, FP32
     ptab = 16 * 600 * 128 * 8                         # row phasors of 16 steps, [mode][row] FP32 pairs
     assert fp >= g32 + ring + ptab
@@ -120,14 +120,13 @@ def test_statistics_slots_of_the_launch_shape(lib, shape, store, qset, slots):
     """The statistics slots the layout reserves follow the launch-shape rule:
     periodic lattices hold the two distribution buffers, the statistics and
     under 1 MiB of small tables, so the slot count is read off the footprint.
-    FP32 stores keep FP64 sums per slot; 16-bit stores keep one set of FP64
-    totals and FP32 window sums per slot."""
+    Every store keeps one set of FP64 totals and FP32 window sums per slot."""
     from paper_2205_02774_amd import make_desc, footprint
     nx, ny, nz = shape
     fp = footprint(make_desc(nx, ny, nz, nu_lb=1e-3, store=store, periodic_x=True, velocity_set=qset))
     g = 2 * qset * nx * ny * nz * (4 if store == "f32" else 2)
     bins = 9 * nx * ny
-    need = slots * bins * 8 if store == "f32" else bins * 8 + slots * bins * 4
+    need = bins * 8 + slots * bins * 4
     assert need <= fp - g < need + 2 ** 20
 
 
@@ -138,9 +137,9 @@ def test_velocity_set_and_collision_validation(lib):
     f15 = footprint(make_desc(64, 32, 32, nu_lb=1e-3, periodic_x=True, velocity_set=15))
     g19 = 2 * 19 * 64 * 32 * 32 * 4
     # FP32 statistics launches of D3Q15 / D3Q19 run two z waves per block, so
-    # this lattice has 16 FP64 slots of 9 x 64 x 32 sums where D3Q27 (one z
-    # wave per block) has 32.
-    slot = 9 * 64 * 32 * 8
+    # this lattice has 16 slots of 9 x 64 x 32 FP32 window sums where D3Q27
+    # (one z wave per block) has 32.
+    slot = 9 * 64 * 32 * 4
     assert f27 - base == pytest.approx(g19 * 8 / 19 + 16 * slot, abs=1024)
     assert base - f15 == pytest.approx(g19 * 4 / 19, abs=1024)
     assert footprint(make_desc(64, 32, 32, nu_lb=1e-3, periodic_x=True, velocity_set=0)) == base
