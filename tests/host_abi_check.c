@@ -1,6 +1,7 @@
 /* Host-only exercise of libstglbm's C ABI (no device needed): descriptor
- * validation, footprint, unit derivation, status strings and the error paths
- * that return before any HIP call.  Built with AddressSanitizer and
+ * validation, footprint (and with it the launch-shape, statistics-slot and
+ * z-chunk rules over a grid of lattices), unit derivation, status strings and
+ * the error paths that return before any HIP call.  Built with AddressSanitizer and
  * UndefinedBehaviorSanitizer on the host code by tests/test_host_sanitizers.py;
  * prints "ok" and exits 0 when every expectation holds. */
 #include <stdio.h>
@@ -48,6 +49,32 @@ int main(void) {
     v.collision = 1;
     uint64_t b = 0;
     EXPECT(stglbm_footprint(&v, &b) == STGLBM_OK);
+  }
+  /* the launch-shape rules (block shape, statistics slots, unequal z chunks of
+   * the 16-bit stores) over a grid of lattices: ragged and narrow rows, few
+   * and many rows and z slices, every store and velocity set, both boundary
+   * kinds; the footprint always holds the two distribution buffers */
+  {
+    static const int nxs[] = {2, 48, 64, 100, 448, 512, 520, 1024, 1030};
+    static const int nys[] = {2, 3, 7, 64, 128, 256, 300};
+    static const int nzs[] = {1, 2, 3, 7, 33, 64, 96, 256, 512, 1000};
+    static const int qs[] = {15, 19, 27};
+    for (unsigned a = 0; a < sizeof nxs / sizeof nxs[0]; ++a)
+      for (unsigned b = 0; b < sizeof nys / sizeof nys[0]; ++b)
+        for (unsigned c = 0; c < sizeof nzs / sizeof nzs[0]; ++c)
+          for (int store = 0; store <= 2; ++store)
+            for (unsigned k = 0; k < 3; ++k)
+              for (int per = 0; per <= 1; ++per) {
+                stglbm_lattice_desc v = channel(nxs[a], nys[b], nzs[c]);
+                v.store = store;
+                v.velocity_set = qs[k];
+                v.periodic_x = per;
+                if (per || nxs[a] < 12) v.sponge_cells = 0;
+                uint64_t fb = 0;
+                const uint64_t cells = (uint64_t)nxs[a] * nys[b] * nzs[c];
+                EXPECT(stglbm_footprint(&v, &fb) == STGLBM_OK);
+                EXPECT(fb >= 2ull * qs[k] * cells * (store == STGLBM_F32 ? 4 : 2));
+              }
   }
   /* invalid descriptors: each fails on the host with a message */
   stglbm_lattice_desc bad[8];

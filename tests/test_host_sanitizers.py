@@ -2,8 +2,10 @@
 
 Builds the library's host code (api.hip) with the sanitizers on the host side
 only, the kernel units unchanged, links tests/host_abi_check.c against them,
-and runs it: descriptor validation, footprint, unit derivation, status
-strings and the argument checks that return before any HIP call.  The
+and runs it: descriptor validation, footprint (the launch-shape,
+statistics-slot and z-chunk rules over 11,340 lattice descriptors), unit
+derivation, status strings and the argument checks that return before any
+HIP call.  The
 two-buffer pull scheme of the kernels is race-free by construction (each
 launch reads one buffer and writes the other); determinism is checked on the
 GPU by the parity tests.
