@@ -55,6 +55,20 @@ def test_step_noalloc_matches_step_twice():
     na.close()
 
 
+@pytest.mark.parametrize("store", ["f16", "bf16"])
+def test_step_noalloc_matches_step_16bit(store):
+    # 16-bit statistics launches of 512-cell rows: stglbm_step makes the inlet
+    # planes in the step kernel's trailing blocks from the 15th step on, the
+    # allocation-free variant with the plane kernel into the scratch; the two
+    # give the same planes, so f and the statistics agree bit for bit
+    ref, na = _pair(small_channel(512, 8, 40, n_modes=30, seed=5, store=store))
+    ref.profile(True)
+    _compare(ref, na, (23, 17, 2))
+    assert ref.profile_read()["tail_planes"] > 0
+    ref.close()
+    na.close()
+
+
 def test_step_noalloc_rejects_planes_beyond_the_scratch():
     from paper_2205_02774_amd import Lattice, abi
     # one inlet plane of 2 x 700,000 nodes is 16.8 MB, above the 16 MiB scratch
