@@ -33,8 +33,11 @@ HBM_PEAK_GBS = 8000.0                       # MI355X HBM3E
 # microseconds per launch, which would otherwise land in ms_per_step.
 PROFILE_EVERY = 8
 PROFILES = os.path.join(ROOT, "profiles")
+# What makes the step kernels: the units that instantiate them, the headers
+# they include and the build script (it sets the FP32 unit's scheduler).
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2205_02774_amd", "csrc", f)
-               for f in ("lattice_step.h", "stg_block.h", "stglbm_internal.h", "lattice_kernels.hip")]
+               for f in ("lattice_step.h", "stg_block.h", "stglbm_internal.h", "lattice_kernels.hip",
+                         "lattice_f32.hip")] + [os.path.join(ROOT, "paper_2205_02774_amd", "build.py")]
 
 
 def log(msg):

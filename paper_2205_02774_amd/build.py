@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libstglbm.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
-           ("lattice_kernels.hip", "lattice_variants.hip", "inlet_kernels.hip", "api.hip")]
+           ("lattice_kernels.hip", "lattice_variants.hip", "lattice_f32.hip", "inlet_kernels.hip", "api.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
@@ -16,6 +16,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
 ]
+# Per-unit flags: the FP32 statistics kernel is scheduled for instruction-level
+# parallelism (measured faster there; slower for the 16-bit and forced kernels).
+UNIT_FLAGS = {"lattice_f32.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 NOISE = "packed-fp32-ops"
 # roctx ranges around the host entry points (rocprofv3 --marker-trace)
 LINK = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
@@ -34,7 +37,8 @@ def build(verbose=False):
     inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
     with tempfile.TemporaryDirectory(prefix="stglbm_build_") as tmpdir:
         objs = [os.path.join(tmpdir, os.path.basename(src) + ".o") for src in SOURCES]
-        cmds = [[HIPCC, *FLAGS, *inc, "-c", src, "-o", obj] for src, obj in zip(SOURCES, objs)]
+        cmds = [[HIPCC, *FLAGS, *UNIT_FLAGS.get(os.path.basename(src), []), *inc, "-c", src, "-o", obj]
+                for src, obj in zip(SOURCES, objs)]
         with concurrent.futures.ThreadPoolExecutor(max_workers=len(cmds)) as pool:
             results = list(pool.map(_run, cmds))
         for cmd, (rc, msgs) in zip(cmds, results):

@@ -3,7 +3,8 @@
 // helpers every configuration shares: fill, copy, sponge factors, export and
 // import of f, the equilibrium start state and the velocity probes.  The
 // stream-collide kernel itself is in lattice_step.h; the velocity-set and
-// operator variants are instantiated in lattice_variants.hip.
+// operator variants are instantiated in lattice_variants.hip, and the FP32
+// statistics kernel of the channel steps in lattice_f32.hip.
 //
 // Mapping: a wave owns 64 consecutive x cells of one (y, z) row (times the
 // cells per lane), so each population load and store of a wave is one

@@ -721,6 +721,15 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
   }
 }
 
+}  // namespace
+
+// The FP32 D3Q19 regularized statistics kernel without a body force (one cell
+// per lane) is instantiated in its own unit, lattice_f32.hip, which the build
+// compiles with the machine scheduler set for instruction-level parallelism.
+hipError_t launch_f32_d3q19_stats(const StepParams& p, dim3 grid, dim3 block, size_t lds, hipStream_t s);
+
+namespace {
+
 template <class Codec, int QN, bool REG, int V>
 hipError_t launch_step_v(const StepParams& p, bool stats, hipStream_t s) {
   const dim3 block(64 * p.wx, p.wz);
@@ -735,8 +744,12 @@ hipError_t launch_step_v(const StepParams& p, bool stats, hipStream_t s) {
     if (stats) step_kernel<Codec, QN, REG, V, true, true><<<grid, block, lds, s>>>(p);
     else step_kernel<Codec, QN, REG, V, false, true><<<grid, block, lds, s>>>(p);
   } else {
-    if (stats) step_kernel<Codec, QN, REG, V, true, false><<<grid, block, lds, s>>>(p);
-    else step_kernel<Codec, QN, REG, V, false, false><<<grid, block, lds, s>>>(p);
+    if constexpr (std::is_same_v<Codec, CodecF32> && QN == 19 && REG && V == 1) {
+      if (stats) return launch_f32_d3q19_stats(p, grid, block, lds, s);
+    } else {
+      if (stats) step_kernel<Codec, QN, REG, V, true, false><<<grid, block, lds, s>>>(p);
+    }
+    if (!stats) step_kernel<Codec, QN, REG, V, false, false><<<grid, block, lds, s>>>(p);
   }
   return hipGetLastError();
 }

@@ -16,13 +16,14 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 
 
 def test_kernel_hash_covers_the_stream_collide_sources():
-    """The hash covers the unit that instantiates the step kernel and every
-    library header it includes, directly or not."""
+    """The hash covers the units that instantiate the step kernels of the
+    channel workloads, every library header they include, directly or not,
+    and the build script that sets their compile flags."""
     import re
     sys.path.insert(0, ROOT)
     import bench
     csrc = os.path.join(ROOT, "paper_2205_02774_amd", "csrc")
-    seen, todo = set(), ["lattice_kernels.hip"]
+    seen, todo = set(), ["lattice_kernels.hip", "lattice_f32.hip"]
     while todo:
         f = todo.pop()
         if f in seen or not os.path.exists(os.path.join(csrc, f)):
@@ -30,7 +31,7 @@ def test_kernel_hash_covers_the_stream_collide_sources():
         seen.add(f)
         todo += re.findall(r'#include "([^"]+)"', open(os.path.join(csrc, f)).read())
     assert "stg_block.h" in seen and "lattice_step.h" in seen
-    assert {os.path.basename(p) for p in bench.KERNEL_SRCS} == seen
+    assert {os.path.basename(p) for p in bench.KERNEL_SRCS} == seen | {"build.py"}
     h = bench.kernel_hash()
     assert len(h) == 16 and h == bench.kernel_hash()
 

@@ -29,7 +29,8 @@ SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined
 def test_host_abi_under_asan_ubsan(tmp_path):
     flags = ["--offload-arch=gfx950", "-O1", "-fPIC", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
              "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
-    units = [("lattice_kernels.hip", []), ("lattice_variants.hip", []), ("inlet_kernels.hip", []), ("api.hip", SAN)]
+    units = [("lattice_kernels.hip", []), ("lattice_variants.hip", []), ("lattice_f32.hip", []),
+             ("inlet_kernels.hip", []), ("api.hip", SAN)]
     cmds = [[HIPCC, *flags, *extra, "-c", os.path.join(CSRC, src), "-o", str(tmp_path / (src + ".o"))]
             for src, extra in units]
     with concurrent.futures.ThreadPoolExecutor(len(cmds)) as pool:
