@@ -723,10 +723,15 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
 
 }  // namespace
 
-// The FP32 D3Q19 regularized statistics kernel without a body force (one cell
-// per lane) is instantiated in its own unit, lattice_f32.hip, which the build
-// compiles with the machine scheduler set for instruction-level parallelism.
-hipError_t launch_f32_d3q19_stats(const StepParams& p, dim3 grid, dim3 block, size_t lds, hipStream_t s);
+// FP32 statistics kernels without a body force (one cell per lane) that run
+// faster scheduled for instruction-level parallelism: D3Q19 regularized (the
+// channel's), D3Q15 regularized and D3Q19 plain BGK.  They are instantiated
+// in their own unit, lattice_f32.hip, which the build compiles with that
+// machine-scheduler strategy.
+template <int QN, bool REG>
+constexpr bool kIlpUnit = (QN == 19 && REG) || (QN == 15 && REG) || (QN == 19 && !REG);
+template <int QN, bool REG>
+hipError_t launch_f32_stats(const StepParams& p, dim3 grid, dim3 block, size_t lds, hipStream_t s);
 
 namespace {
 
@@ -744,8 +749,8 @@ hipError_t launch_step_v(const StepParams& p, bool stats, hipStream_t s) {
     if (stats) step_kernel<Codec, QN, REG, V, true, true><<<grid, block, lds, s>>>(p);
     else step_kernel<Codec, QN, REG, V, false, true><<<grid, block, lds, s>>>(p);
   } else {
-    if constexpr (std::is_same_v<Codec, CodecF32> && QN == 19 && REG && V == 1) {
-      if (stats) return launch_f32_d3q19_stats(p, grid, block, lds, s);
+    if constexpr (std::is_same_v<Codec, CodecF32> && V == 1 && kIlpUnit<QN, REG>) {
+      if (stats) return launch_f32_stats<QN, REG>(p, grid, block, lds, s);
     } else {
       if (stats) step_kernel<Codec, QN, REG, V, true, false><<<grid, block, lds, s>>>(p);
     }
