@@ -16,8 +16,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
 ]
-# Per-unit flags: the FP32 statistics kernel is scheduled for instruction-level
-# parallelism (measured faster there; slower for the 16-bit and forced kernels).
+# Per-unit flags: lattice_f32.hip holds FP32 statistics kernels scheduled for
+# instruction-level parallelism (measured faster there; slower for the 16-bit
+# and forced kernels, which stay in the default units).
 UNIT_FLAGS = {"lattice_f32.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 NOISE = "packed-fp32-ops"
 # roctx ranges around the host entry points (rocprofv3 --marker-trace)

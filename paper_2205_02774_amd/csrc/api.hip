@@ -59,6 +59,7 @@ struct Layout {
   int zsched = 0;                     // statistics launches: unequal z chunks, slot s on rows zbeg[s] .. zbeg[s + 1] - 1
   int zbeg[kMaxZChunks + 1] = {};
   int tail_planes = 1;                // statistics launches may make the next inlet plane in trailing blocks
+  int f32_ilp = 0;                    // FP32 D3Q19 statistics launches: the max-ilp build of the kernel
 };
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -189,6 +190,7 @@ Layout make_layout(const stglbm_lattice_desc* d) {
   if (const char* env = std::getenv("STGLBM_REMAP")) L.remap_env = std::atoi(env) ? 1 : 0;
   if (const char* env = std::getenv("STGLBM_LOCKSTEP")) L.lockstep = std::atoi(env) ? 1 : 0;
   if (const char* env = std::getenv("STGLBM_TAIL_STG")) L.tail_planes = std::atoi(env) ? 1 : 0;
+  if (const char* env = std::getenv("STGLBM_F32_ILP")) L.f32_ilp = std::atoi(env) ? 1 : 0;
   L.vec = vec;
   L.nxt = (d->nx + 64 * vec - 1) / (64 * vec);
   const int wx_row = L.nxt < 8 ? L.nxt : 8;   // whole rows of up to 8 tiles
@@ -454,6 +456,7 @@ StepParams step_params(stglbm_t h) {
   p.win = h->at<float>(h->L.win);
   p.win_first = 0;
   p.flag = h->at<int>(h->L.flag);
+  p.f32_ilp = h->L.f32_ilp;
   return p;
 }
 

@@ -1,14 +1,15 @@
-// FP32-store statistics kernels without a body force (one cell per lane):
-// D3Q19 regularized, the kernel of the FP32 channel steps (two z waves of
-// whole rows per block), and the D3Q15 regularized and D3Q19 plain-BGK
-// variants.  They are the kernel of lattice_step.h, instantiated in a unit of
-// their own so that the build can compile them with the AMDGPU machine
-// scheduler set for instruction-level parallelism (max-ilp).  Measured on
-// MI355X at 512x128x256: D3Q19 regularized 0.4563 against 0.4594 ms per
-// launch (three alternating runs of 1000 steps), D3Q15 0.3643 against 0.3668,
-// D3Q19 BGK 0.4580 against 0.4653; the same strategy slowed the 16-bit
-// launches, the FP32 launch with a body force and FP32 D3Q27, which keep the
-// default schedule.
+// FP32-store statistics kernels without a body force (one cell per lane),
+// instantiated in a unit of their own so that the build can compile them
+// with the AMDGPU machine scheduler set for instruction-level parallelism
+// (max-ilp): the D3Q15 regularized and D3Q19 plain-BGK variants, which it
+// makes faster (512x128x256, 500 steps after 2000: D3Q15 0.3643 against
+// 0.3668 ms per launch, BGK 0.4580 against 0.4653), and a second build of the
+// channel's D3Q19 regularized kernel.  That one is 1 % faster in long runs
+// (0.4551 against 0.4588 ms over 200 launches) but slower over its first ten
+// or so launches in a process (0.4580 against 0.4559 ms over launches 6-25),
+// so the default-schedule build stays the default and this one is chosen by
+// the STGLBM_F32_ILP tuning override.  The 16-bit kernels, the kernels with a
+// body force and FP32 D3Q27 measured slower with max-ilp.
 #include "lattice_step.h"
 
 namespace stglbm {

@@ -723,13 +723,13 @@ __global__ __launch_bounds__(64 * step_max_waves(sizeof(typename Codec::storage)
 
 }  // namespace
 
-// FP32 statistics kernels without a body force (one cell per lane) that run
-// faster scheduled for instruction-level parallelism: D3Q19 regularized (the
-// channel's), D3Q15 regularized and D3Q19 plain BGK.  They are instantiated
-// in their own unit, lattice_f32.hip, which the build compiles with that
-// machine-scheduler strategy.
+// FP32 statistics kernels without a body force (one cell per lane) built
+// with the machine scheduler set for instruction-level parallelism, in their
+// own unit, lattice_f32.hip: D3Q15 regularized and D3Q19 plain BGK always;
+// D3Q19 regularized (the channel's) when p.f32_ilp is set, its default being
+// the copy built here with the default schedule.
 template <int QN, bool REG>
-constexpr bool kIlpUnit = (QN == 19 && REG) || (QN == 15 && REG) || (QN == 19 && !REG);
+constexpr bool kIlpUnit = (QN == 15 && REG) || (QN == 19 && !REG);
 template <int QN, bool REG>
 hipError_t launch_f32_stats(const StepParams& p, dim3 grid, dim3 block, size_t lds, hipStream_t s);
 
@@ -752,6 +752,9 @@ hipError_t launch_step_v(const StepParams& p, bool stats, hipStream_t s) {
     if constexpr (std::is_same_v<Codec, CodecF32> && V == 1 && kIlpUnit<QN, REG>) {
       if (stats) return launch_f32_stats<QN, REG>(p, grid, block, lds, s);
     } else {
+      if constexpr (std::is_same_v<Codec, CodecF32> && V == 1 && QN == 19 && REG) {
+        if (stats && p.f32_ilp) return launch_f32_stats<QN, REG>(p, grid, block, lds, s);
+      }
       if (stats) step_kernel<Codec, QN, REG, V, true, false><<<grid, block, lds, s>>>(p);
     }
     if (!stats) step_kernel<Codec, QN, REG, V, false, false><<<grid, block, lds, s>>>(p);

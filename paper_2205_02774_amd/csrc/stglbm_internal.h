@@ -93,6 +93,9 @@ struct StepParams {
   // s take z rows zbeg[s] .. zbeg[s + 1] - 1 (multiples of wz rows)
   int zsched;
   int zbeg[kMaxZChunks + 1];
+  // FP32 D3Q19 regularized statistics launches: the kernel built with the
+  // max-ilp machine scheduler instead of the default one
+  int f32_ilp;
 };
 
 // Statistics: every launch adds its per-slot sums to FP32 window sums; after kStatsWindow sampled steps (counted from stats_reset) they
