@@ -539,23 +539,22 @@ def test_unequal_z_chunks_match_uniform_chunks(store, monkeypatch):
         assert nrm < 1e-6
 
 
-@pytest.mark.parametrize("qset,collision", [(19, "regularized"), (15, "regularized"), (19, "bgk")])
-def test_fp32_scheduler_builds_agree(qset, collision, monkeypatch):
-    """The FP32 statistics kernels built with the max-ilp machine scheduler
-    (the D3Q15 and BGK variants always, the D3Q19 regularized one under the
-    tuning override STGLBM_F32_ILP=1) compute exactly what the default build
-    does: same source, same arithmetic, only the instruction order differs.
-    An inlet/outlet channel of whole 512-cell rows (two z waves per block)
-    over 20 sampled steps gives bit-identical f and statistics with the
-    override on and off; the D3Q19 regularized run is also held to the
-    oracle's bar."""
+def test_fp32_scheduler_builds_agree(monkeypatch):
+    """The FP32 D3Q19 regularized statistics kernel exists in two builds: the
+    default one and one compiled with the max-ilp machine scheduler (tuning
+    override STGLBM_F32_ILP=1).  Same source and arithmetic, only the
+    instruction order differs, so an inlet/outlet channel of whole 512-cell
+    rows (two z waves per block) gives bit-identical f and statistics over 20
+    sampled steps with either, and meets the oracle's bar.  (The D3Q15 and
+    plain-BGK FP32 statistics kernels have only the max-ilp build; the
+    variant tests hold them to the oracle.)"""
     from paper_2205_02774_amd import channel_from_config
     cfg = small_channel(512, 8, 16, n_modes=30, seed=12)
     runs = {}
     for ilp in ("0", "1"):
         monkeypatch.setenv("STGLBM_F32_ILP", ilp)
-        print(f"[gpu] scheduler builds D3Q{qset} {collision} ilp={ilp}", flush=True)
-        lat = channel_from_config(cfg, store="f32", device="cuda:0", velocity_set=qset, collision=collision)
+        print(f"[gpu] scheduler builds ilp={ilp}", flush=True)
+        lat = channel_from_config(cfg, store="f32", device="cuda:0")
         lat.stats_reset()
         lat.step(20)
         st, n = lat.get_stats()
@@ -565,9 +564,8 @@ def test_fp32_scheduler_builds_agree(qset, collision, monkeypatch):
     assert n0 == n1 == 20
     np.testing.assert_array_equal(f1, f0)
     np.testing.assert_array_equal(s1, s0)
-    if qset == 19 and collision == "regularized":
-        ora = OracleChannel.from_config(cfg)
-        ora.step(20)
-        rel = _rel(f1, ora.f)
-        print(f"[gpu] scheduler builds: max rel err vs oracle {rel.max():.3e}", flush=True)
-        assert rel.max() < FP32_F_TOL
+    ora = OracleChannel.from_config(cfg)
+    ora.step(20)
+    rel = _rel(f1, ora.f)
+    print(f"[gpu] scheduler builds: max rel err vs oracle {rel.max():.3e}", flush=True)
+    assert rel.max() < FP32_F_TOL
